@@ -1,0 +1,240 @@
+"""FDTD-Bath oracle: plain CPU FP64 reference (TEST INFRASTRUCTURE ONLY).
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the GPU library.  The time step itself
+is plain C (fdtd_oracle.c, loops over cells in the paper's order); this
+module builds it with gcc, drives it through ctypes, and maps a workload
+description onto it.  Closed forms used to pin it live in closed_form.py; the
+learned-closure reference (forward, backpropagation through time, Adam) lives
+in closure.py.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import closed_form
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fdtd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math: IEEE FP64)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.c_int, C.c_long, C.c_long, C.c_long, C.c_double]
+        L.or_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.or_add_dielectric.argtypes = [C.c_void_p, _lp, _lp, C.c_double]
+        L.or_add_drude.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double]
+        L.or_add_lorentz_bath.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double,
+                                          C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_add_closure.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                     C.c_double, C.c_double, C.c_int, _dp, _dp]
+        L.or_add_source.argtypes = [C.c_void_p, C.c_int, _lp, _lp, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.or_add_dft.argtypes = [C.c_void_p, C.c_int, _lp, _lp, C.c_int, _dp]
+        L.or_add_energy.argtypes = [C.c_void_p, _lp, _lp, C.c_int]
+        L.or_step.argtypes = [C.c_void_p, C.c_long]
+        L.or_get_step.restype = C.c_long
+        L.or_get_step.argtypes = [C.c_void_p]
+        L.or_get_field.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.or_set_field.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.or_get_P.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_get_Y.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_get_hidden.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp]
+        L.or_set_P.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_set_Y.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_drive_material.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, C.c_long, _dp]
+        L.or_get_dft.argtypes = [C.c_void_p, C.c_int, _dp, C.c_void_p]
+        L.or_energy_count.restype = C.c_long
+        L.or_energy_count.argtypes = [C.c_void_p, C.c_int]
+        L.or_get_energy.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.or_destroy.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _box(b):
+    return np.asarray(b[0], dtype=np.int64), np.asarray(b[1], dtype=np.int64)
+
+
+def bath_arrays(mat):
+    """(omega_j, gamma_j, k_j) of a LorentzBath description, via the oracle's own Table-1 map."""
+    if mat.n_bath == 0:
+        return None, None, None
+    if mat.form is not None:
+        return closed_form.table1_bath(mat.form, mat.omega0, mat.gamma0, mat.n_bath, mat.width,
+                                       mat.bath_gamma, mat.dephasing)
+    return (np.asarray(mat.omega_j, np.float64), np.asarray(mat.gamma_j, np.float64),
+            np.asarray(mat.k_j, np.float64))
+
+
+class Oracle:
+    """One FP64 grid on the CPU, set up from a workload description."""
+
+    def __init__(self, problem, closures: Optional[Dict[int, dict]] = None):
+        self.p = problem
+        L = lib()
+        n = problem.n
+        self.g = L.or_create(problem.ndim, n[0], n[1], n[2], problem.courant)
+        if not self.g:
+            raise ValueError("oracle: bad grid")
+        self._keep = []
+        for a in range(problem.ndim):
+            L.or_set_boundary(self.g, a, int(problem.bc[a]), int(problem.pml_cells[a]), float(problem.pml_R0))
+        closures = closures or {}
+        for mi, m in enumerate(problem.materials):
+            lo, hi = _box(m.box)
+            kind = type(m).__name__
+            if kind == "Dielectric":
+                rc = L.or_add_dielectric(self.g, lo, hi, m.eps_inf)
+            elif kind == "Drude":
+                rc = L.or_add_drude(self.g, lo, hi, m.omega_p, m.gamma, m.eps_inf)
+            elif kind == "LorentzBath":
+                sig = None if m.sigma_cells is None else np.ascontiguousarray(m.sigma_cells, np.float64).ravel()
+                self._keep.append(sig)
+                if mi in closures:
+                    cl = closures[mi]
+                    w = np.ascontiguousarray(cl["weights"], np.float64)
+                    s = np.ascontiguousarray(cl["scales"], np.float64)
+                    rc = L.or_add_closure(self.g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
+                                          float(cl["sum_kc"]), int(cl["width"]), w, s)
+                else:
+                    wj, gj, kj = bath_arrays(m)
+                    self._keep += [wj, gj, kj]
+                    rc = L.or_add_lorentz_bath(self.g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
+                                               m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj))
+            else:
+                raise TypeError(kind)
+            if rc != 0:
+                raise ValueError(f"oracle: material {mi} rejected")
+        for s in problem.sources:
+            lo, hi = _box(s.box)
+            prof = None if s.profile is None else np.ascontiguousarray(s.profile, np.float64).ravel()
+            self._keep.append(prof)
+            if L.or_add_source(self.g, s.comp, lo, hi, s.omega_c, s.width, s.amplitude, _ptr(prof)) < 0:
+                raise ValueError("oracle: bad source")
+        for d in problem.dfts:
+            lo, hi = _box(d.box)
+            om = np.ascontiguousarray(d.omega, np.float64)
+            if L.or_add_dft(self.g, d.axis, lo, hi, len(om), om) < 0:
+                raise ValueError("oracle: bad dft")
+        for e in problem.energies:
+            lo, hi = _box(e.box)
+            if L.or_add_energy(self.g, lo, hi, e.every) < 0:
+                raise ValueError("oracle: bad energy monitor")
+
+    def __del__(self):
+        g = getattr(self, "g", None)
+        if g:
+            lib().or_destroy(g)
+            self.g = None
+
+    def step(self, n: int):
+        lib().or_step(self.g, int(n))
+
+    @property
+    def steps_done(self) -> int:
+        return lib().or_get_step(self.g)
+
+    def field(self, comp: int) -> np.ndarray:
+        out = np.zeros(self.p.cells, np.float64)
+        lib().or_get_field(self.g, comp, out)
+        return out.reshape(self.p.n)
+
+    def set_field(self, comp: int, values: np.ndarray):
+        lib().or_set_field(self.g, comp, np.ascontiguousarray(values, np.float64).ravel())
+
+    def polarization(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
+        m = self.p.materials[mi]
+        nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
+        out = np.zeros(nc, np.float64)
+        if lib().or_get_P(self.g, mi, comp, level, out) != 0:
+            raise ValueError("no polarization")
+        return out
+
+    def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
+        m = self.p.materials[mi]
+        nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
+        out = np.zeros(m.n_bath * nc, np.float64)
+        if lib().or_get_Y(self.g, mi, comp, level, out) != 0:
+            raise ValueError("no bath")
+        return out.reshape(m.n_bath, nc)
+
+    def set_polarization(self, mi: int, comp: int, level: int, values: np.ndarray):
+        if lib().or_set_P(self.g, mi, comp, level, np.ascontiguousarray(values, np.float64).ravel()) != 0:
+            raise ValueError("no polarization")
+
+    def set_bath(self, mi: int, comp: int, level: int, values: np.ndarray):
+        if lib().or_set_Y(self.g, mi, comp, level, np.ascontiguousarray(values, np.float64).ravel()) != 0:
+            raise ValueError("no bath")
+
+    def drive(self, mi: int, comp: int, e_seq: np.ndarray) -> np.ndarray:
+        """Advance material mi alone under a prescribed E sequence; returns P of its first cell."""
+        e = np.ascontiguousarray(e_seq, np.float64)
+        out = np.zeros(len(e), np.float64)
+        if lib().or_drive_material(self.g, mi, comp, e, len(e), out) != 0:
+            raise ValueError("cannot drive")
+        return out
+
+    def hidden(self, mi: int, comp: int) -> np.ndarray:
+        m = self.p.materials[mi]
+        nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
+        out = np.zeros(4 * nc, np.float64)
+        if lib().or_get_hidden(self.g, mi, comp, out) != 0:
+            raise ValueError("no closure")
+        return out.reshape(nc, 4)
+
+    def flux(self, mid: int, raw: bool = False):
+        d = self.p.dfts[mid]
+        nf = len(d.omega)
+        out = np.zeros(nf, np.float64)
+        npts = int(np.prod([d.box[1][a] - d.box[0][a] for a in range(3)]))
+        r = np.zeros(4 * npts * nf * 2, np.float64) if raw else None
+        lib().or_get_dft(self.g, mid, out, _ptr(r))
+        if raw:
+            rr = r.reshape(4, npts, nf, 2)
+            return out, rr[..., 0] + 1j * rr[..., 1]
+        return out
+
+    def energy(self, mid: int) -> np.ndarray:
+        n = lib().or_energy_count(self.g, mid)
+        out = np.zeros(3 * max(n, 0), np.float64)
+        if n > 0:
+            lib().or_get_energy(self.g, mid, out)
+        return out.reshape(-1, 3)
+
+
+def run(problem, steps: Optional[int] = None, closures=None) -> Oracle:
+    o = Oracle(problem, closures=closures)
+    o.step(problem.steps if steps is None else steps)
+    return o

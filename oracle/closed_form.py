@@ -1,0 +1,200 @@
+"""Closed forms for pinning the FDTD-Bath oracle (TEST INFRASTRUCTURE ONLY).
+
+Units: c = eps0 = 1, dx = 1, angular frequencies.  Time dependence exp(-i w t)
+as in the paper's Fourier transforms (Sec. II.A-B), so a DFT with kernel
+exp(+i w t) turns d/dt into -i w.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# ------------------------------------------------------------------ Table 1 (Sec. III)
+def table1_bath(form: str, omega0: float, gamma0: float, nb: int, width: float, bath_gamma: float,
+                dephasing: float):
+    """Bath parameters of the 'uniform' / 'lorentzian' / 'gaussian' forms (Table 1 and its footnote).
+
+    Frequencies evenly spaced on [omega0 - width/2, omega0 + width/2], one
+    damping bath_gamma for all, k_b = sqrt(2 dw dephasing / pi) with
+    dw = width / (nb - 1) (eq:bath_dephasing_value_uniform), and for the
+    non-uniform forms k_j^2 modulated by a Lorentzian / Gaussian of linewidth
+    Gamma = gamma0 + dephasing.
+    """
+    w = np.array([omega0 - width / 2 + width * j / (nb - 1) for j in range(nb)], dtype=np.float64)
+    dw = width / (nb - 1)
+    kb = np.sqrt(2.0 * dw / np.pi * dephasing)
+    G = gamma0 + dephasing
+    if form == "uniform":
+        k = np.full(nb, kb)
+    elif form == "lorentzian":
+        k = kb * np.sqrt(G ** 2 / (G ** 2 + (w - omega0) ** 2))
+    elif form == "gaussian":
+        k = kb * np.exp(-(w - omega0) ** 2 / (4.0 * G ** 2))
+    else:
+        raise ValueError(form)
+    return w, np.full(nb, float(bath_gamma)), k
+
+
+# ------------------------------------------------------------------ continuum susceptibilities (Sec. II)
+def chi_lorentz(w, omega0, gamma, sigma):
+    """eq:chi_L."""
+    w = np.asarray(w, dtype=np.complex128)
+    return omega0 ** 2 * sigma / (omega0 ** 2 - w ** 2 - 1j * gamma * w)
+
+
+def self_energy(w, wj, gj, kj):
+    """eq:chi_LB_self_energy: Sigma(w) = sum_j k_j^2 w^2 / (w_j^2 - w^2 - i g_j w)."""
+    w = np.asarray(w, dtype=np.complex128)[..., None]
+    return np.sum(kj ** 2 * w ** 2 / (wj ** 2 - w ** 2 - 1j * gj * w), axis=-1)
+
+
+def chi_lorentz_bath(w, omega0, gamma0, sigma, wj, gj, kj):
+    """eq:chi_LB."""
+    w = np.asarray(w, dtype=np.complex128)
+    return omega0 ** 2 * sigma / (omega0 ** 2 - w ** 2 - 1j * gamma0 * w - self_energy(w, wj, gj, kj))
+
+
+def gamma_lb(w, gamma0, wj, gj, kj):
+    """eq:gamma_LB: gamma0 + Im Sigma / w."""
+    return gamma0 + np.imag(self_energy(w, wj, gj, kj)) / np.asarray(w)
+
+
+def omega_lb_sq(w, omega0, wj, gj, kj):
+    """eq:omega_LB: omega0^2 - Re Sigma."""
+    return omega0 ** 2 - np.real(self_energy(w, wj, gj, kj))
+
+
+# ------------------------------------------------------------------ discrete (lattice) symbols
+def s2(w, dt):
+    """Symbol of the centred second difference: (2/dt)^2 sin^2(w dt / 2)."""
+    return (2.0 / dt * np.sin(np.asarray(w) * dt / 2.0)) ** 2
+
+
+def s1(w, dt):
+    """Symbol of the centred first difference: sin(w dt) / dt."""
+    return np.sin(np.asarray(w) * dt) / dt
+
+
+def chi_discrete(w, dt, omega0, gamma0, sigma, wj=None, gj=None, kj=None, drude=False):
+    """Susceptibility of the three-level recurrences at frequency w.
+
+    Substituting X^n = X exp(-i w n dt) in the central-difference forms of
+    eq:finite-difference-scheme turns the second difference into -s2 and the
+    first into -i s1; eliminating the bath with eq:EOM_LorentzBath-2 gives
+    chi = w0^2 sigma / (w0^2 - s2 - i g0 s1 - s1^2 sum_j k_j^2 / (w_j^2 - s2 - i g_j s1)).
+    For Drude, pass omega0 = omega_p, sigma = 1 and drude=True (no restoring term).
+    """
+    w = np.asarray(w, dtype=np.float64)
+    S2, S1 = s2(w, dt), s1(w, dt)
+    restore = 0.0 if drude else omega0 ** 2
+    den = restore - S2 - 1j * gamma0 * S1
+    if wj is not None and len(wj):
+        den = den - (S1 ** 2) * np.sum(kj ** 2 / (wj ** 2 - S2[..., None] - 1j * gj * S1[..., None]), axis=-1)
+    return omega0 ** 2 * sigma / den
+
+
+def lattice_k(w, dt):
+    """Vacuum lattice wavenumber: sin(k/2) = sin(w dt/2) / dt (dx = 1, Courant = dt)."""
+    return 2.0 * np.arcsin(np.sin(np.asarray(w) * dt / 2.0) / dt)
+
+
+def group_velocity(w, dt):
+    """d w / d k of the vacuum lattice dispersion: cos(k/2) / cos(w dt / 2)."""
+    k = lattice_k(w, dt)
+    return np.cos(k / 2.0) / np.cos(np.asarray(w) * dt / 2.0)
+
+
+def phase_velocity(w, dt):
+    return np.asarray(w) / lattice_k(w, dt)
+
+
+def lattice_transmission(w, dt, eps_cells, chi_cells):
+    """|t|^2 of a 1D layer stack on the Yee lattice, vacuum on both sides.
+
+    The lattice Helmholtz equation E_{j+1} - 2E_j + E_{j-1} + s2 (eps_j + chi_j) E_j = 0
+    is integrated from a pure transmitted wave exp(i k j) behind the stack back
+    to the front, where the field splits into incident and reflected lattice
+    plane waves.  eps_cells: (L,) background; chi_cells: (L, nw) complex.
+    """
+    w = np.atleast_1d(np.asarray(w, dtype=np.float64))
+    L = len(eps_cells)
+    k = lattice_k(w, dt)
+    S2 = s2(w, dt)
+    # cells L, L+1 are vacuum, carrying exp(i k j)
+    e_next = np.exp(1j * k * (L + 1))
+    e_cur = np.exp(1j * k * L)
+    for j in range(L - 1, -3, -1):
+        # recurrence at node j+1 gives E_j from E_{j+1}, E_{j+2}
+        node = j + 1
+        if 0 <= node < L:
+            fac = 2.0 - S2 * (eps_cells[node] + chi_cells[node])
+        else:
+            fac = 2.0 - S2
+        e_prev = fac * e_cur - e_next
+        e_next, e_cur = e_cur, e_prev
+    # now e_cur = E_{-2}, e_next = E_{-1}; E_j = A exp(ikj) + B exp(-ikj)
+    jm2, jm1 = -2, -1
+    det = np.exp(1j * k * jm2) * np.exp(-1j * k * jm1) - np.exp(-1j * k * jm2) * np.exp(1j * k * jm1)
+    A = (e_cur * np.exp(-1j * k * jm1) - e_next * np.exp(-1j * k * jm2)) / det
+    return 1.0 / np.abs(A) ** 2
+
+
+# ------------------------------------------------------------------ closed-box modes and Rabi roots
+def closed_box_K2(N: int):
+    """Eigenvalues K_m^2 of the lattice curl-curl on N nodes with H(-1/2) = 0, E(N) = 0.
+
+    Modes E_j = cos(k (j + 1/2)) with k (N + 1/2) = (m - 1/2) pi, K^2 = 4 sin^2(k/2).
+    """
+    m = np.arange(1, N + 1)
+    k = (2 * m - 1) * np.pi / (2 * N + 1)
+    return 4.0 * np.sin(k / 2.0) ** 2
+
+
+def rabi_lattice_omegas(K2, dt, omega0, sigma, eps_inf=1.0):
+    """Both polariton frequencies of a mode K^2 in a filled lossless Lorentz medium.
+
+    Roots of eps s^4 - s^2 (eps w0^2 + w0^2 sigma + K^2) + K^2 w0^2 = 0 in X = s^2,
+    mapped back by w = (2/dt) arcsin(s dt / 2).
+    """
+    a = eps_inf
+    b = -(eps_inf * omega0 ** 2 + omega0 ** 2 * sigma + K2)
+    c = K2 * omega0 ** 2
+    disc = np.sqrt(b * b - 4 * a * c)
+    X = np.stack([(-b - disc) / (2 * a), (-b + disc) / (2 * a)])
+    return 2.0 / dt * np.arcsin(np.sqrt(X) * dt / 2.0)
+
+
+def rabi_continuum(K2, omega0, sigma, eps_inf=1.0):
+    """Continuum polariton pair (dt -> 0): roots of eps w^4 - w^2 (eps w0^2 + w0^2 sigma + K^2) + K^2 w0^2."""
+    a = eps_inf
+    b = -(eps_inf * omega0 ** 2 + omega0 ** 2 * sigma + K2)
+    c = K2 * omega0 ** 2
+    disc = np.sqrt(b * b - 4 * a * c)
+    return np.sqrt(np.stack([(-b - disc) / (2 * a), (-b + disc) / (2 * a)]))
+
+
+# ------------------------------------------------------------------ stability
+def lossless_margin(dt, ndim, eps_inf, omega0=0.0, sigma=0.0, drude_wp=None):
+    """Left side of the explicit-scheme stability condition (>= 0: stable).
+
+    With X = s^2 <= 4/dt^2 required for every lattice mode, the larger root of the
+    dispersion quadratic must not pass 4/dt^2:
+      eps (4/dt^2 - w0^2) - w0^2 sigma - K2max (1 - w0^2 dt^2 / 4) >= 0,  K2max = 4 ndim.
+    Drude: eps 4/dt^2 - w_p^2 - K2max >= 0.
+    """
+    K2 = 4.0 * ndim
+    if drude_wp is not None:
+        return eps_inf * 4.0 / dt ** 2 - drude_wp ** 2 - K2
+    return eps_inf * (4.0 / dt ** 2 - omega0 ** 2) - omega0 ** 2 * sigma - K2 * (1.0 - omega0 ** 2 * dt ** 2 / 4.0)
+
+
+# ------------------------------------------------------------------ bath-dephasing consistency (Sec. III)
+def lorentzian_bath_im_I_approx(w, omega0, Gamma, gamma_b):
+    """Approximate Im I(w) for the Lorentzian bath: (pi w / 2) G (G + gb/2) / ((w - w0)^2 + (G + gb/2)^2)."""
+    G2 = Gamma + gamma_b / 2.0
+    return np.pi * w / 2.0 * Gamma * G2 / ((w - omega0) ** 2 + G2 ** 2)
+
+
+def gamma_polariton(Xc2, gamma_c, Xm2, gamma_m):
+    """eq:gamma_polariton."""
+    return Xc2 * gamma_c + Xm2 * gamma_m
