@@ -73,7 +73,10 @@ def config2_3d(nx: int = 256, ny: int = 256, steps: int = 5000, nb: int = 8, nfr
                dtype: str = "f32", seed: int = 1002, sigma_window=None) -> Problem:
     """nx x ny x 512, periodic x,y; z: PML 32 | vac 12 | Drude 12 | LB 400 | Drude 12 | vac 12 | PML 32.
 
-    sigma ~ U[0.01, 0.1] per cell of the LB layer.  The field is drawn for the
+    sigma ~ U[0.01, 0.1] per cell of the LB layer.  The 12-cell Drude mirrors
+    at omega_p = 10 are opaque (amplitude transmission ~1e-24), so the plane
+    source (z = 66) and the flux plane (z = 446) sit inside the cavity, 10
+    cells from the layer edges, as for the 1D cavity.  The field is drawn for the
     full 256 x 256 plane; a crop (nx, ny < 256) takes its corner, or the window
     sigma_window = (x0, y0) of it, so a crop sees the same sigma values as the
     full grid there.
@@ -96,8 +99,8 @@ def config2_3d(nx: int = 256, ny: int = 256, steps: int = 5000, nb: int = 8, nfr
                     sigma_cells=sig, n_bath=nb, omega_j=w, gamma_j=g, k_j=k),
         Drude(box(*full_xy, (edges[4], edges[5])), **MIRROR),
     ]
-    p.sources.append(gaussian_pulse(0, box(*full_xy, (38, 39))))
-    p.dfts.append(DftFlux(2, box(*full_xy, (474, 475)), freq_grid(nfreq)))
+    p.sources.append(gaussian_pulse(0, box(*full_xy, (edges[3] + 10, edges[3] + 11))))
+    p.dfts.append(DftFlux(2, box(*full_xy, (edges[4] - 10, edges[4] - 9)), freq_grid(nfreq)))
     return p
 
 

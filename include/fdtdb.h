@@ -1,0 +1,248 @@
+/*
+ * fdtdb — FDTD-Bath time stepping on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the FDTD scheme with auxiliary bath fields of T. E. Li,
+ * "FDTD with Auxiliary Bath Fields for Condensed-Phase Polaritonics"
+ * (arXiv 2505.23963): a Yee leapfrog (H from curl E, D from curl H,
+ * E = (D - P)/eps_inf, Sec. II and eq:FDTD-1D) in which each cell's
+ * polarization P follows a Lorentz oscillator coupled to N_b explicit
+ * harmonic bath coordinates (eq:EOM_LorentzBath), advanced with the
+ * central-difference updates eq:Pz_update-LB and eq:Yzj_finite_difference,
+ * one independent bath per E component (end of Sec. II.C).
+ *
+ * Conventions
+ *   Units c = eps0 = mu0 = 1, cell size dx = 1, dt = courant * dx, angular
+ *   frequencies.  Cells are indexed (i, j, k) over axes (x, y, z); memory is
+ *   C order with z fastest.  Yee placement of cell (i,j,k):
+ *     Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
+ *     Hx (i,j+1/2,k+1/2)  Hy (i+1/2,j,k+1/2)  Hz (i+1/2,j+1/2,k)
+ *   A 1D grid runs along x with (Ez, Hy); a 2D grid is the x-y plane with
+ *   (Ez, Hx, Hy); unused axes have extent 1.  Component ids: 0..2 = Ex, Ey,
+ *   Ez; 3..5 = Hx, Hy, Hz.
+ *   Time: after k full steps, H is at t = k dt; E, D and P at (k + 1/2) dt.
+ *   Boxes are half-open cell ranges [lo, hi) per axis.
+ *
+ * Ownership: the library owns every device buffer it allocates; host arrays
+ * passed in are copied before the call returns and never retained; outputs
+ * go to caller-owned host buffers.  A grid borrows the caller's HIP stream
+ * (or creates its own when given NULL) and never destroys a borrowed stream.
+ *
+ * Errors: every entry point returns an fdtdb_status; no exception crosses
+ * the boundary.  fdtdb_last_error() returns a thread-local message for the
+ * last failing call on the calling thread.
+ *
+ * Threading: calls on one grid must not overlap; distinct grids are
+ * independent.
+ */
+#ifndef FDTDB_H
+#define FDTDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtdb_grid_s *fdtdb_grid;
+
+typedef enum {
+    FDTDB_OK = 0,
+    FDTDB_E_INVALID = -1,   /* bad argument, box outside the grid, overlapping materials, ... */
+    FDTDB_E_NOMEM = -2,     /* device or host allocation failed */
+    FDTDB_E_DEVICE = -3,    /* a HIP call failed, or no usable device */
+    FDTDB_E_UNSTABLE = -4,  /* parameters violate the explicit-scheme stability bound */
+    FDTDB_E_DIVERGED = -5,  /* the watchdog found a non-finite field */
+    FDTDB_E_STATE = -6      /* call not allowed in the grid's current state */
+} fdtdb_status;
+
+typedef enum { FDTDB_F32 = 0, FDTDB_F64 = 1 } fdtdb_dtype;
+
+/* Boundary per axis.  CLOSED: field values beyond the grid read as zero
+ * (electric wall one node past the high end, magnetic wall half a node
+ * before the low end; lossless).  PML: the same walls behind a CPML layer of
+ * pml_cells cells on both ends.  PERIODIC: wrap-around. */
+typedef enum { FDTDB_BC_PML = 0, FDTDB_BC_PERIODIC = 1, FDTDB_BC_CLOSED = 2 } fdtdb_bc;
+
+typedef struct {
+    int64_t lo[3], hi[3];
+} fdtdb_box;
+
+typedef struct {
+    int ndim;                 /* 1, 2 or 3 */
+    int64_t n[3];             /* cells per axis (unused axes: 1) */
+    double courant;           /* dt / dx; the library checks the vacuum Courant limit 1/sqrt(ndim) */
+    fdtdb_dtype dtype;        /* storage precision of the time-stepped state */
+    fdtdb_bc bc[3];           /* per axis; unused axes are forced to PERIODIC */
+    int pml_cells[3];         /* CPML thickness per axis (used where bc == PML) */
+    double pml_R0;            /* nominal CPML reflection (<= 0: 1e-8) */
+    void *hip_stream;         /* hipStream_t to enqueue on; NULL: the grid creates its own stream */
+} fdtdb_grid_desc;
+
+/* ------------------------------------------------------------------------------------------ grid */
+
+/* Allocate a grid with all fields zero.  Fails with E_INVALID on a bad
+ * descriptor, E_UNSTABLE when courant exceeds 1/sqrt(ndim), E_NOMEM/E_DEVICE
+ * on allocation or device errors. */
+fdtdb_status fdtdb_create_grid(const fdtdb_grid_desc *desc, fdtdb_grid *out);
+
+/* Free every device buffer of the grid; the grid's own stream (if any) is destroyed. */
+fdtdb_status fdtdb_destroy_grid(fdtdb_grid g);
+
+/* ------------------------------------------------------------------------------------- materials */
+/* Materials are boxes; boxes must not overlap each other, and dispersive
+ * boxes must not overlap the CPML layers (E_INVALID).  Materials can only be
+ * added before the first fdtdb_step (E_STATE afterwards).  *material_id
+ * (nullable) receives the material's index. */
+
+/* Non-dispersive background eps_inf > 0 (D = eps_inf E). */
+fdtdb_status fdtdb_set_eps_inf(fdtdb_grid g, const fdtdb_box *box, double eps_inf, int *material_id);
+
+/* Drude medium: P'' + gamma P' = omega_p^2 E, i.e. the Lorentz model of
+ * eq:EOM_Lorentz with omega0^2 dropped from the restoring term and
+ * omega0^2 sigma = omega_p^2 (Sec. II.A).  E_UNSTABLE when
+ * eps_inf < dt^2 (omega_p^2 + 4 ndim) / 4 (the lossless lattice bound). */
+fdtdb_status fdtdb_set_drude(fdtdb_grid g, const fdtdb_box *box, double omega_p, double gamma, double eps_inf,
+                             int *material_id);
+
+/* Lorentz-Bath medium (eq:EOM_LorentzBath; parameters of eq:chi_LB):
+ *   omega0, gamma0   bright-mode frequency and phenomenological damping
+ *   eps_inf          background permittivity (E = (D - P)/eps_inf)
+ *   sigma_cells      per-cell oscillator strength over the box, C order (x,y,z),
+ *                    box-sized; NULL: sigma_uniform everywhere
+ *   n_bath           bath modes per cell and E component (0: plain Lorentz, eq:Pz_1D_Lorentz)
+ *   omega_j, gamma_j, k_j  bath frequencies, dampings and couplings (n_bath each)
+ * E_UNSTABLE when the lossless lattice bound
+ *   eps_inf (4/dt^2 - omega0^2) - omega0^2 sigma_max - 4 ndim (1 - omega0^2 dt^2 / 4) >= 0
+ * fails, or when any omega_j dt >= 2 or omega0 dt >= 2. */
+fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double omega0, double gamma0,
+                                    double eps_inf, const double *sigma_cells, double sigma_uniform, int n_bath,
+                                    const double *omega_j, const double *gamma_j, const double *k_j,
+                                    int *material_id);
+
+/* Host-only map of Table 1 (Sec. III): bath form 0 = uniform, 1 = lorentzian,
+ * 2 = gaussian.  Frequencies evenly spaced on [omega0 - width/2, omega0 + width/2],
+ * gamma_j = bath_gamma, k_b = sqrt(2 dw dephasing / pi) with dw = width/(n_bath-1)
+ * (eq:bath_dephasing_value_uniform); the non-uniform forms multiply k_b by
+ * sqrt(G^2/(G^2 + (w_j - omega0)^2)) or exp(-(w_j - omega0)^2/(4 G^2)), G = gamma0 + dephasing.
+ * Outputs are caller arrays of n_bath doubles.  n_bath >= 2. */
+fdtdb_status fdtdb_bath_params(int form, double omega0, double gamma0, int n_bath, double width,
+                               double bath_gamma, double dephasing, double *omega_j, double *gamma_j,
+                               double *k_j);
+
+/* ---------------------------------------------------------------------------- sources, monitors */
+
+/* Soft current source on E component `component` over `box`:
+ *   J(t) = amplitude exp(-(t - t0)^2 / (2 tau^2)) cos(omega_c (t - t0)),
+ *   tau = 1/width, t0 = 5 tau, J = 0 for t > 2 t0,
+ * subtracted in the D update: D^{n+1/2} += -dt J(t_n) profile(cell).
+ * profile: box-sized per-cell weights (NULL: 1).  The box must lie in one
+ * eps_inf (E_INVALID otherwise).  *source_id is nullable. */
+fdtdb_status fdtdb_add_source(fdtdb_grid g, int component, const fdtdb_box *box, double omega_c, double width,
+                              double amplitude, const double *profile, int *source_id);
+
+/* DFT flux plane normal to `axis`, one cell thick (plane->hi[axis] = plane->lo[axis] + 1),
+ * through the E nodes at index p0 = plane->lo[axis].  Accumulated in FP64:
+ *   E~_c(p, w) = dt sum_{n} E_c^{n+1/2}(p) e^{i w (n+1/2) dt}
+ *   H~_c(p, w) = dt sum_{n} (1/2)(H_c^{n+1}(p0 - 1/2) + H_c^{n+1}(p0 + 1/2)) e^{i w (n+1) dt}
+ * for the two tangential components, and the flux along +axis
+ *   Phi(w) = Re sum_p (E~ x conj(H~)) . e_axis. */
+fdtdb_status fdtdb_add_dft_flux(fdtdb_grid g, int axis, const fdtdb_box *plane, int nfreq, const double *omega,
+                                int *monitor_id);
+
+/* Exact discrete energy over a box, sampled at steps n = 0, every, 2 every, ...
+ * (Hamiltonian density eq:H_full in the centred-difference form):
+ *   field = sum eps_inf/2 E^{n-1/2}.E^{n+1/2} + 1/2 |H^n|^2
+ *   pol   = sum rho/2 [((P^{n+1/2}-P^{n-1/2})/dt)^2 + omega0^2 P^{n+1/2} P^{n-1/2}]
+ *   bath  = sum rho/2 sum_j [((Y_j^{n+1/2}-Y_j^{n-1/2})/dt)^2 + omega_j^2 Y_j^{n+1/2} Y_j^{n-1/2}]
+ * with rho = 1/(sigma omega0^2) (Drude: 1/omega_p^2).  FP64 sums. */
+fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int every, int *monitor_id);
+
+/* -------------------------------------------------------------------------------------- stepping */
+
+/* Enqueue nsteps full time steps on the grid's stream and return without
+ * waiting.  The first call uploads coefficient tables and fixes the
+ * material layout.  Work is replayed from captured HIP graphs when graph
+ * mode is on (fdtdb_set_graph). */
+fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps);
+
+/* Wait for the grid's stream; runs the non-finite-field watchdog and returns
+ * E_DIVERGED if it trips, E_DEVICE on an asynchronous device error. */
+fdtdb_status fdtdb_synchronize(fdtdb_grid g);
+
+/* Number of full steps enqueued so far. */
+fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps);
+
+/* Graph mode: 0 = direct launches; > 0 = capture chunks of this many steps
+ * (rounded up to an even count) and replay them. Requires a non-NULL stream. */
+fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps);
+
+/* ------------------------------------------------------------------------------------- read-out */
+/* All read-outs synchronize the grid's stream first. */
+
+/* flux: nfreq doubles.  raw (nullable): [4][npts][nfreq][2] doubles, the
+ * complex accumulators of E_t1, E_t2, H_t1, H_t2 (t1, t2 cyclic after axis). */
+fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int monitor_id, double *flux, double *raw);
+
+/* out: capacity x 3 doubles [field, pol, bath]; *n_samples receives the number recorded. */
+fdtdb_status fdtdb_energy(fdtdb_grid g, int monitor_id, double *out, int64_t capacity, int64_t *n_samples);
+
+/* Copy a field component to a host array of n[0]*n[1]*n[2] doubles (converted to FP64). */
+fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, double *out);
+
+/* Overwrite a field component from n[0]*n[1]*n[2] host doubles (rounded to the storage type). */
+fdtdb_status fdtdb_set_field(fdtdb_grid g, int component, const double *in);
+
+/* Polarization of a dispersive material, E component c, at level 0 (P^{n+1/2})
+ * or 1 (P^{n-1/2}); box-sized host doubles.  For Drude only the difference
+ * level0 - level1 is stored; level 1 then returns zero and level 0 the difference. */
+fdtdb_status fdtdb_get_polarization(fdtdb_grid g, int material_id, int component, int level, double *out);
+
+/* Bath coordinates [n_bath][box cells] at level 0 (Y^{n+1/2}) or 1 (Y^{n-1/2}). */
+fdtdb_status fdtdb_get_bath(fdtdb_grid g, int material_id, int component, int level, double *out);
+
+/* ---------------------------------------------------------------------------------- diagnostics */
+
+typedef struct {
+    int64_t cells;                 /* total cells */
+    int64_t dispersive_cells;      /* cells carrying P */
+    int64_t bath_cells;            /* cells carrying explicit bath modes */
+    double bytes_per_step;         /* algorithmic HBM bytes of one full step (state read once, written once) */
+    double bytes_per_step_e;       /* ... of the E/material update alone */
+    double bytes_per_step_h;       /* ... of the H update alone */
+    int launches_per_step;         /* kernel launches in one step (direct mode) */
+} fdtdb_stats;
+
+fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out);
+
+/* Per-launch timing.  When on, fdtdb_step launches directly (no graph
+ * replay) and brackets every E and H region launch with HIP events on the
+ * grid's stream; fdtdb_kernel_records collects them. */
+fdtdb_status fdtdb_set_profiling(fdtdb_grid g, int on);
+
+typedef struct {
+    int region;                    /* region index (boxes of uniform update kind) */
+    int phase;                     /* 0: E / material update, 1: H update */
+    int kind;                      /* 0 background, 1 Drude, 2 Lorentz-Bath, 3 learned closure */
+    int n_bath;                    /* explicit bath modes per component (kind 2) */
+    int pml;                       /* 1 if the region carries CPML terms */
+    int64_t cells;                 /* cells updated per launch */
+    double bytes;                  /* algorithmic HBM bytes per launch */
+    double ms_total;               /* summed event time of the profiled launches */
+    int64_t launches;              /* profiled launches */
+} fdtdb_kernel_record;
+
+/* Synchronize, fold pending event pairs into the records and copy up to
+ * capacity records (two per region) to out; *count receives the number. */
+fdtdb_status fdtdb_kernel_records(fdtdb_grid g, fdtdb_kernel_record *out, int capacity, int *count);
+
+/* Last error message on this thread ("" if none). */
+const char *fdtdb_last_error(void);
+
+/* Library version string. */
+const char *fdtdb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTDB_H */

@@ -1,0 +1,9 @@
+"""fdtdb: the FDTD-Bath time step (arXiv 2505.23963) on AMD MI355X (gfx950).
+
+The compute path is libfdtdb.so (hand-written HIP kernels behind the C-ABI
+of include/fdtdb.h); this package is its thin ctypes binding.
+"""
+from .fdtdb import (BC_CLOSED, BC_PERIODIC, BC_PML, F32, F64, FdtdbError, Grid, bath_params,  # noqa: F401
+                    lib)
+
+__all__ = ["Grid", "FdtdbError", "bath_params", "lib"]

@@ -1,0 +1,113 @@
+// Internal types shared by the host runtime and the HIP kernels of libfdtdb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdtdb {
+
+constexpr int kMaxSources = 8;
+constexpr int kMaxEnergy = 4;
+constexpr int kBlock = 256;          // threads per block of the stencil kernels
+constexpr int kDftSlots = 32;        // steps staged before a DFT flush
+constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
+
+// Update kind of a region.
+enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3 };
+
+// Curl axes of component c: (curl F)_c = d_{a1} F_{a2} - d_{a2} F_{a1}.
+__host__ __device__ constexpr int curl_a1(int c) { return c == 0 ? 1 : (c == 1 ? 2 : 0); }
+__host__ __device__ constexpr int curl_a2(int c) { return c == 0 ? 2 : (c == 1 ? 0 : 1); }
+
+// Active components per dimension: 1D {Ez; Hy}, 2D {Ez; Hx, Hy}, 3D all.
+__host__ __device__ constexpr bool e_active(int dim, int c) { return dim == 3 || c == 2; }
+__host__ __device__ constexpr bool h_active(int dim, int c) { return dim == 3 || (dim == 2 ? c < 2 : c == 1); }
+// Axis a carries derivatives in a grid of this dimension.
+__host__ __device__ constexpr bool axis_live(int dim, int a) { return a < dim; }
+
+// Device clock: advanced once per step by the tick kernel, read by the others.
+struct Clock {
+    long long step;                  // index n of the step in progress
+    long long next;                  // index of the next step
+    double amp[kMaxSources];         // J(t_n) of each source
+};
+
+struct SourceDev {
+    int comp;
+    int lo[3], hi[3];
+    double omega_c, tau, t0, amplitude;
+    double coef;                     // dt / eps_inf at the source cells
+    const double *profile;           // box-sized, or null
+};
+
+struct EnergyDev {
+    int lo[3], hi[3];
+    int every;
+    double *partial;                 // [block][3] for this monitor
+};
+
+// Arguments of the E / material update of one region.
+struct EArgs {
+    void *E[3];
+    const void *H[3];
+    int n[3];
+    int per[3];                      // 1: periodic axis, 0: values beyond the grid are zero
+    int lo[3], ext[3];               // region box
+    int ext12;                       // ext[1] * ext[2]
+    double dt, inv_eps;
+    // CPML (background regions): psi per E component and curl term, coefficient tables per axis
+    void *psi[3][2];
+    const double *pml_b[3], *pml_c[3];
+    // material box and state
+    int mlo[3], mext[3];
+    long long mcells;
+    void *Pcur[3], *Pnew[3];         // bath/Lorentz: two ping-pong levels; Drude: Pcur = V (read/write)
+    void *Ycur[3], *Ynew[3];         // bath: [group][mcells] of 4-vectors
+    const void *sigma;               // per material cell (storage type), or null
+    double sigma0;
+    const double *coef;              // FP64 coefficient table of the material
+    void *hid[3];                    // learned closure hidden state [mcells][4]
+    const float *cw;                 // learned closure weights (FP32)
+    // sources and clock
+    const Clock *clock;
+    const SourceDev *src;
+    int nsrc;
+    // energy monitors
+    int nen;
+    EnergyDev en[kMaxEnergy];
+    long long block_base;            // first partial slot of this launch
+};
+
+struct HArgs {
+    const void *E[3];
+    void *H[3];
+    int n[3];
+    int per[3];
+    int lo[3], ext[3];
+    int ext12;
+    double dt;
+    void *psi[3][2];
+    const double *pml_b[3], *pml_c[3];
+};
+
+struct DftArgs {
+    int axis, npts;
+    int lo[3], ext[3], ext12;
+    int n[3], per[3];
+    const void *E[2];        // tangential E (t1, t2) or null
+    const void *H[2];
+    double *stage;           // [slot][4][npts]
+    int slot;
+};
+
+// Coefficient table layout of a bath / Lorentz material (FP64):
+//   [0] cE = w0^2 dt^2 / A      [1] cP = (w0^2 dt^2 - 2) / A
+//   [2] cPm = (1 - g0 dt/2 - (dt/2) sum k c) / A
+//   [3] rho0 = 1 / w0^2 (energy; rho = rho0 / sigma)   [4] w0^2   [5..7] unused
+//   then per mode j (stride 8): a_j, b_j + 1, c_j, sa_j, sb_j, w_j^2, unused, unused
+//   with sa_j = (dt/2) k_j a_j / A and sb_j = (dt/2) k_j b_j / A.
+// Drude table: [0] dE = wp^2 dt^2 / (1 + g dt/2)  [1] dV = (1 - g dt/2)/(1 + g dt/2)  [2] rho = 1/wp^2.
+constexpr int kCoefHead = 8;
+constexpr int kCoefMode = 8;
+
+}  // namespace fdtdb

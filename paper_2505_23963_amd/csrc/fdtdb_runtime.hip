@@ -1,0 +1,1135 @@
+// Host runtime and C-ABI of libfdtdb: grid layout, material tables, validation,
+// region partition, launch sequencing, HIP graph capture and read-out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtdb.h"
+#include "fdtdb_internal.h"
+
+namespace fdtdb {
+hipError_t launch_update_e(int dim, bool f64, const EArgs &a, int kind, int ng, bool pml, bool energy, hipStream_t s);
+hipError_t launch_update_h(int dim, bool f64, const HArgs &a, bool pml, hipStream_t s);
+hipError_t launch_tick(Clock *clk, const SourceDev *src, int nsrc, double dt, hipStream_t s);
+hipError_t launch_energy_reduce(const Clock *clk, const double *partial, long long nslots, int every, double *out,
+                                long long capacity, hipStream_t s);
+
+hipError_t launch_dft_stage(bool f64, const DftArgs &a, hipStream_t s);
+hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int nslots, double dt, double *tw,
+                            const double *stage, int npts, double2 *acc, hipStream_t s);
+hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s);
+hipError_t launch_nonfinite(bool f64, const void *f, long long n, int *flag, hipStream_t s);
+}  // namespace fdtdb
+
+using namespace fdtdb;
+
+namespace {
+
+thread_local std::string g_err;
+
+fdtdb_status fail(fdtdb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(x)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(FDTDB_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(x)                          \
+    do {                                \
+        fdtdb_status s_ = (x);          \
+        if (s_ != FDTDB_OK) return s_;  \
+    } while (0)
+
+struct Material {
+    int kind = K_BACKGROUND;
+    int64_t lo[3], hi[3];
+    int mext[3];
+    long long mcells = 0;
+    double eps = 1.0, omega0 = 0.0, gamma0 = 0.0, sigma0 = 0.0, sigma_max = 0.0;
+    bool sigma_per_cell = false;
+    int nb = 0, ng = 0;
+    std::vector<double> wj, gj, kj, coef;
+    void *P[2][3] = {};
+    void *Y[2][3] = {};
+    void *sigma_dev = nullptr;
+    double *coef_dev = nullptr;
+};
+
+struct Region {
+    int lo[3], hi[3];
+    int mat = -1;
+    int pml_mask = 0;
+    double eps = 1.0;
+    void *psiE[3][2] = {};
+    void *psiH[3][2] = {};
+    bool energy = false;
+    long long block_base = 0;
+    long long cells() const { return (long long)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+};
+
+struct Pending {
+    int rec;
+    hipEvent_t a, b;
+};
+
+struct Source {
+    int comp;
+    int64_t lo[3], hi[3];
+    double omega_c, width, amplitude, eps;
+    std::vector<double> profile;
+    double *profile_dev = nullptr;
+};
+
+struct Dft {
+    int axis;
+    int64_t lo[3], hi[3];
+    int npts, nf;
+    int t1, t2;
+    std::vector<double> omega;
+    double *omega_dev = nullptr, *stage = nullptr, *tw = nullptr, *flux_dev = nullptr;
+    double2 *acc = nullptr;
+    int nstaged = 0;
+};
+
+struct Energy {
+    int64_t lo[3], hi[3];
+    int every;
+    double *partial = nullptr;
+    long long nslots = 0;
+    double *out = nullptr;
+    long long capacity = 0;
+};
+
+size_t words(long long n, bool f64) { return (size_t)n * (f64 ? 8 : 4); }
+
+}  // namespace
+
+struct fdtdb_grid_s {
+    int ndim = 3;
+    int n[3] = {1, 1, 1};
+    long long ncell = 0;
+    double dt = 0.5, R0 = 1e-8;
+    bool f64 = false;
+    int bc[3], pml[3];
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *E[3] = {}, *H[3] = {};
+    std::vector<Material> mats;
+    std::vector<Source> srcs;
+    std::vector<Dft> dfts;
+    std::vector<Energy> ens;
+    std::vector<Region> regions;
+    double *pml_b[3] = {}, *pml_c[3] = {}, *pml_bh[3] = {}, *pml_ch[3] = {};
+    Clock *clock = nullptr;
+    SourceDev *src_dev = nullptr;
+    int *flag_dev = nullptr;
+    bool finalized = false;
+    long long steps = 0;          // steps enqueued
+    long long total_blocks = 0;   // E-kernel blocks over all regions (energy partial slots)
+    // graphs
+    int graph_chunk = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_parity = 0;
+    int launches_per_step = 0;
+    std::vector<void *> allocs;
+    // profiling
+    bool profiling = false;
+    std::vector<fdtdb_kernel_record> records;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+
+    fdtdb_status alloc(void **p, size_t bytes) {
+        if (bytes == 0) bytes = 8;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) return fail(FDTDB_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        e = hipMemset(*p, 0, bytes);
+        if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
+        allocs.push_back(*p);
+        return FDTDB_OK;
+    }
+    size_t esize() const { return f64 ? 8 : 4; }
+};
+
+namespace {
+
+bool box_ok(const fdtdb_grid_s *g, const fdtdb_box *b) {
+    if (!b) return false;
+    for (int a = 0; a < 3; a++)
+        if (b->lo[a] < 0 || b->hi[a] > g->n[a] || b->lo[a] >= b->hi[a]) return false;
+    return true;
+}
+
+bool overlap(const int64_t *alo, const int64_t *ahi, const int64_t *blo, const int64_t *bhi) {
+    for (int a = 0; a < 3; a++)
+        if (ahi[a] <= blo[a] || bhi[a] <= alo[a]) return false;
+    return true;
+}
+
+bool in_pml(const fdtdb_grid_s *g, const int64_t *lo, const int64_t *hi) {
+    for (int a = 0; a < 3; a++) {
+        if (g->bc[a] != FDTDB_BC_PML) continue;
+        if (lo[a] < g->pml[a] || hi[a] > g->n[a] - g->pml[a]) return true;
+    }
+    return false;
+}
+
+fdtdb_status check_new_material(fdtdb_grid_s *g, const fdtdb_box *box, bool dispersive) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "materials must be set before the first step");
+    if (!box_ok(g, box)) return fail(FDTDB_E_INVALID, "material box outside the grid or empty");
+    for (auto &m : g->mats)
+        if (overlap(box->lo, box->hi, m.lo, m.hi)) return fail(FDTDB_E_INVALID, "material boxes overlap");
+    if (in_pml(g, box->lo, box->hi))
+        return fail(FDTDB_E_INVALID, dispersive ? "dispersive material inside the CPML layer"
+                                                : "material inside the CPML layer (the layer assumes eps_inf = 1)");
+    if (g->mats.size() >= 4096) return fail(FDTDB_E_INVALID, "too many materials");
+    return FDTDB_OK;
+}
+
+Material &new_material(fdtdb_grid_s *g, const fdtdb_box *box, int kind) {
+    g->mats.emplace_back();
+    Material &m = g->mats.back();
+    m.kind = kind;
+    m.mcells = 1;
+    for (int a = 0; a < 3; a++) {
+        m.lo[a] = box->lo[a];
+        m.hi[a] = box->hi[a];
+        m.mext[a] = (int)(box->hi[a] - box->lo[a]);
+        m.mcells *= m.mext[a];
+    }
+    return m;
+}
+
+// CPML conductivity s(d) = s_max (d/L)^3, s_max = -4 ln(R0) / (2L); E nodes at integer
+// positions, H nodes half a cell further along the axis.
+double pml_sigma(const fdtdb_grid_s *g, int a, double pos) {
+    if (g->bc[a] != FDTDB_BC_PML) return 0.0;
+    const double L = (double)g->pml[a];
+    const double smax = -4.0 * std::log(g->R0) / (2.0 * L);
+    double d = 0.0;
+    if (pos < L) d = L - pos;
+    else if (pos > (double)(g->n[a] - 1) - L) d = pos - ((double)(g->n[a] - 1) - L);
+    if (d <= 0.0) return 0.0;
+    const double r = d / L;
+    return smax * r * r * r;
+}
+
+// ---------------------------------------------------------------------------- region partition
+fdtdb_status build_regions(fdtdb_grid_s *g) {
+    std::vector<int> br[3];
+    for (int a = 0; a < 3; a++) {
+        br[a].push_back(0);
+        br[a].push_back(g->n[a]);
+        if (g->bc[a] == FDTDB_BC_PML && a < g->ndim) {
+            br[a].push_back(g->pml[a]);
+            br[a].push_back(g->n[a] - g->pml[a]);
+        }
+        for (auto &m : g->mats) {
+            br[a].push_back((int)m.lo[a]);
+            br[a].push_back((int)m.hi[a]);
+        }
+        std::sort(br[a].begin(), br[a].end());
+        br[a].erase(std::unique(br[a].begin(), br[a].end()), br[a].end());
+    }
+    const int na = (int)br[0].size() - 1, nb = (int)br[1].size() - 1, nc = (int)br[2].size() - 1;
+    // attribute of each atom: (mat, pml mask)
+    std::vector<int> attr((size_t)na * nb * nc);
+    std::map<std::pair<int, int>, int> ids;
+    auto key = [&](int x, int y, int z) { return ((size_t)x * nb + y) * nc + z; };
+    for (int x = 0; x < na; x++)
+        for (int y = 0; y < nb; y++)
+            for (int z = 0; z < nc; z++) {
+                const int64_t lo[3] = {br[0][x], br[1][y], br[2][z]};
+                int mat = -1;
+                for (size_t mi = 0; mi < g->mats.size(); mi++) {
+                    const Material &m = g->mats[mi];
+                    if (lo[0] >= m.lo[0] && lo[0] < m.hi[0] && lo[1] >= m.lo[1] && lo[1] < m.hi[1] && lo[2] >= m.lo[2] &&
+                        lo[2] < m.hi[2])
+                        mat = (int)mi;
+                }
+                int mask = 0;
+                for (int a = 0; a < g->ndim; a++)
+                    if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= g->n[a] - g->pml[a])) mask |= 1 << a;
+                auto k = std::make_pair(mat, mask);
+                if (!ids.count(k)) {
+                    int id = (int)ids.size();
+                    ids[k] = id;
+                }
+                attr[key(x, y, z)] = ids[k];
+            }
+    // greedy box growth: z first, then y, then x
+    std::vector<char> used(attr.size(), 0);
+    std::vector<std::pair<int, int>> rev(ids.size());
+    for (auto &kv : ids) rev[kv.second] = kv.first;
+    for (int x = 0; x < na; x++)
+        for (int y = 0; y < nb; y++)
+            for (int z = 0; z < nc; z++) {
+                if (used[key(x, y, z)]) continue;
+                const int id = attr[key(x, y, z)];
+                int z1 = z + 1;
+                while (z1 < nc && !used[key(x, y, z1)] && attr[key(x, y, z1)] == id) z1++;
+                int y1 = y + 1;
+                for (;; y1++) {
+                    if (y1 >= nb) break;
+                    bool ok = true;
+                    for (int zz = z; zz < z1 && ok; zz++) ok = !used[key(x, y1, zz)] && attr[key(x, y1, zz)] == id;
+                    if (!ok) break;
+                }
+                int x1 = x + 1;
+                for (;; x1++) {
+                    if (x1 >= na) break;
+                    bool ok = true;
+                    for (int yy = y; yy < y1 && ok; yy++)
+                        for (int zz = z; zz < z1 && ok; zz++) ok = !used[key(x1, yy, zz)] && attr[key(x1, yy, zz)] == id;
+                    if (!ok) break;
+                }
+                for (int xx = x; xx < x1; xx++)
+                    for (int yy = y; yy < y1; yy++)
+                        for (int zz = z; zz < z1; zz++) used[key(xx, yy, zz)] = 1;
+                Region r;
+                r.lo[0] = br[0][x]; r.hi[0] = br[0][x1];
+                r.lo[1] = br[1][y]; r.hi[1] = br[1][y1];
+                r.lo[2] = br[2][z]; r.hi[2] = br[2][z1];
+                r.mat = rev[id].first;
+                r.pml_mask = rev[id].second;
+                r.eps = r.mat >= 0 ? g->mats[r.mat].eps : 1.0;
+                g->regions.push_back(r);
+            }
+    // CPML psi storage per region, per component and curl term whose axis is absorbing
+    for (auto &r : g->regions) {
+        if (!r.pml_mask) continue;
+        const long long nc_ = r.cells();
+        for (int c = 0; c < 3; c++) {
+            const int ax[2] = {curl_a1(c), curl_a2(c)};
+            for (int t = 0; t < 2; t++) {
+                if (!(r.pml_mask & (1 << ax[t]))) continue;
+                if (e_active(g->ndim, c)) TRY(g->alloc(&r.psiE[c][t], words(nc_, g->f64)));
+                if (h_active(g->ndim, c)) TRY(g->alloc(&r.psiH[c][t], words(nc_, g->f64)));
+            }
+        }
+    }
+    return FDTDB_OK;
+}
+
+bool region_hits_box(const Region &r, const int64_t *lo, const int64_t *hi) {
+    for (int a = 0; a < 3; a++)
+        if (r.hi[a] <= lo[a] || hi[a] <= r.lo[a]) return false;
+    return true;
+}
+
+// algorithmic bytes per cell of a region's E and H launches: each state word read once and
+// written once, neighbour values counted once
+void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh) {
+    const double w = g->f64 ? 8.0 : 4.0;
+    int ne = 0, nh = 0;
+    for (int c = 0; c < 3; c++) { ne += e_active(g->ndim, c); nh += h_active(g->ndim, c); }
+    double e = (2.0 * ne + nh) * w, h = (ne + 2.0 * nh) * w;
+    if (r.pml_mask) {
+        int te = 0, th = 0;
+        for (int c = 0; c < 3; c++)
+            for (int t = 0; t < 2; t++) { te += r.psiE[c][t] != nullptr; th += r.psiH[c][t] != nullptr; }
+        e += 2.0 * te * w;
+        h += 2.0 * th * w;
+    }
+    if (r.mat >= 0) {
+        const Material &m = g->mats[r.mat];
+        if (m.kind == K_DRUDE) e += 2.0 * ne * w;
+        else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * w;
+    }
+    *be = e;
+    *bh = h;
+}
+
+fdtdb_status finalize(fdtdb_grid_s *g) {
+    if (g->finalized) return FDTDB_OK;
+    TRY(build_regions(g));
+    // CPML coefficient tables: b = exp(-s dt), c = b - 1 at E-type and H-type positions
+    for (int a = 0; a < 3; a++) {
+        std::vector<double> b(g->n[a]), c(g->n[a]), bh(g->n[a]), ch(g->n[a]);
+        for (int p = 0; p < g->n[a]; p++) {
+            b[p] = std::exp(-pml_sigma(g, a, (double)p) * g->dt);
+            c[p] = b[p] - 1.0;
+            bh[p] = std::exp(-pml_sigma(g, a, (double)p + 0.5) * g->dt);
+            ch[p] = bh[p] - 1.0;
+        }
+        TRY(g->alloc((void **)&g->pml_b[a], 8 * g->n[a]));
+        TRY(g->alloc((void **)&g->pml_c[a], 8 * g->n[a]));
+        TRY(g->alloc((void **)&g->pml_bh[a], 8 * g->n[a]));
+        TRY(g->alloc((void **)&g->pml_ch[a], 8 * g->n[a]));
+        HIP_TRY(hipMemcpy(g->pml_b[a], b.data(), 8 * g->n[a], hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->pml_c[a], c.data(), 8 * g->n[a], hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->pml_bh[a], bh.data(), 8 * g->n[a], hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->pml_ch[a], ch.data(), 8 * g->n[a], hipMemcpyHostToDevice));
+    }
+    // sources
+    std::vector<SourceDev> sd(g->srcs.size());
+    for (size_t s = 0; s < g->srcs.size(); s++) {
+        Source &S = g->srcs[s];
+        SourceDev &d = sd[s];
+        d.comp = S.comp;
+        for (int a = 0; a < 3; a++) { d.lo[a] = (int)S.lo[a]; d.hi[a] = (int)S.hi[a]; }
+        d.omega_c = S.omega_c;
+        d.tau = 1.0 / S.width;
+        d.t0 = 5.0 * d.tau;
+        d.amplitude = S.amplitude;
+        d.coef = g->dt / S.eps;
+        d.profile = nullptr;
+        if (!S.profile.empty()) {
+            TRY(g->alloc((void **)&S.profile_dev, 8 * S.profile.size()));
+            HIP_TRY(hipMemcpy(S.profile_dev, S.profile.data(), 8 * S.profile.size(), hipMemcpyHostToDevice));
+            d.profile = S.profile_dev;
+        }
+    }
+    TRY(g->alloc((void **)&g->src_dev, sizeof(SourceDev) * std::max<size_t>(1, sd.size())));
+    if (!sd.empty()) HIP_TRY(hipMemcpy(g->src_dev, sd.data(), sizeof(SourceDev) * sd.size(), hipMemcpyHostToDevice));
+    // energy monitors: mark regions, assign partial slots
+    long long base = 0;
+    for (auto &r : g->regions) {
+        r.block_base = base;
+        base += (r.cells() + kBlock - 1) / kBlock;
+        for (auto &e : g->ens)
+            if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
+    }
+    g->total_blocks = base;
+    for (auto &e : g->ens) {
+        e.nslots = base;
+        TRY(g->alloc((void **)&e.partial, 24 * (size_t)base));
+    }
+    g->launches_per_step = 1 + 2 * (int)g->regions.size() + (int)g->ens.size() + (int)g->dfts.size();
+    for (size_t ri = 0; ri < g->regions.size(); ri++) {
+        const Region &r = g->regions[ri];
+        double be, bh;
+        region_bytes(g, r, &be, &bh);
+        for (int ph = 0; ph < 2; ph++) {
+            fdtdb_kernel_record k{};
+            k.region = (int)ri;
+            k.phase = ph;
+            k.kind = ph == 0 && r.mat >= 0 ? g->mats[r.mat].kind : K_BACKGROUND;
+            k.n_bath = r.mat >= 0 ? g->mats[r.mat].nb : 0;
+            k.pml = r.pml_mask != 0;
+            k.cells = r.cells();
+            k.bytes = (ph == 0 ? be : bh) * (double)r.cells();
+            g->records.push_back(k);
+        }
+    }
+    g->finalized = true;
+    return FDTDB_OK;
+}
+
+void fill_fields(const fdtdb_grid_s *g, int *n, int *per) {
+    for (int a = 0; a < 3; a++) {
+        n[a] = g->n[a];
+        per[a] = g->bc[a] == FDTDB_BC_PERIODIC ? 1 : 0;
+    }
+}
+
+fdtdb_status ensure_energy_capacity(fdtdb_grid_s *g, long long last_step) {
+    for (auto &e : g->ens) {
+        const long long need = last_step / e.every + 1;
+        if (need <= e.capacity) continue;
+        long long cap = std::max<long long>(need, std::max<long long>(64, 2 * e.capacity));
+        double *nw = nullptr;
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        TRY(g->alloc((void **)&nw, 24 * (size_t)cap));
+        if (e.out && e.capacity) HIP_TRY(hipMemcpy(nw, e.out, 24 * (size_t)e.capacity, hipMemcpyDeviceToDevice));
+        e.out = nw;   // the old buffer stays in the grid's allocation list until destroy
+        e.capacity = cap;
+        if (g->graph) {   // captured launches hold the old buffer
+            (void)hipGraphExecDestroy(g->graph);
+            g->graph = nullptr;
+        }
+    }
+    return FDTDB_OK;
+}
+
+fdtdb_status flush_dft(fdtdb_grid_s *g, Dft &d) {
+    if (d.nstaged == 0) return FDTDB_OK;
+    HIP_TRY(launch_dft_flush(g->clock, d.omega_dev, d.nf, d.nstaged, g->dt, d.tw, d.stage, d.npts, d.acc, g->stream));
+    d.nstaged = 0;
+    return FDTDB_OK;
+}
+
+hipEvent_t take_event(fdtdb_grid_s *g) {
+    if (!g->pool.empty()) {
+        hipEvent_t e = g->pool.back();
+        g->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+fdtdb_status collect_events(fdtdb_grid_s *g) {
+    if (g->pending.empty()) return FDTDB_OK;
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    for (auto &p : g->pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+        g->records[p.rec].ms_total += ms;
+        g->records[p.rec].launches += 1;
+        g->pool.push_back(p.a);
+        g->pool.push_back(p.b);
+    }
+    g->pending.clear();
+    return FDTDB_OK;
+}
+
+// enqueue one full step (no host synchronization)
+fdtdb_status enqueue_step(fdtdb_grid_s *g) {
+    const long long n = g->steps;
+    const int cur = (int)(n & 1), nxt = cur ^ 1;
+    HIP_TRY(launch_tick(g->clock, g->src_dev, (int)g->srcs.size(), g->dt, g->stream));
+    for (auto &r : g->regions) {
+        EArgs a{};
+        for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
+        fill_fields(g, a.n, a.per);
+        for (int ax = 0; ax < 3; ax++) { a.lo[ax] = r.lo[ax]; a.ext[ax] = r.hi[ax] - r.lo[ax]; }
+        a.ext12 = a.ext[1] * a.ext[2];
+        a.dt = g->dt;
+        a.inv_eps = 1.0 / r.eps;
+        int kind = K_BACKGROUND, ng = 0;
+        for (int c = 0; c < 3; c++)
+            for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiE[c][t];
+        for (int ax = 0; ax < 3; ax++) { a.pml_b[ax] = g->pml_b[ax]; a.pml_c[ax] = g->pml_c[ax]; }
+        if (r.mat >= 0) {
+            Material &m = g->mats[r.mat];
+            kind = m.kind;
+            ng = m.ng;
+            for (int ax = 0; ax < 3; ax++) { a.mlo[ax] = (int)m.lo[ax]; a.mext[ax] = m.mext[ax]; }
+            a.mcells = m.mcells;
+            if (kind == K_DRUDE) {
+                for (int c = 0; c < 3; c++) a.Pcur[c] = m.P[0][c];
+            } else if (kind == K_BATH) {
+                for (int c = 0; c < 3; c++) {
+                    a.Pcur[c] = m.P[cur][c];
+                    a.Pnew[c] = m.P[nxt][c];
+                    a.Ycur[c] = m.Y[cur][c];
+                    a.Ynew[c] = m.Y[nxt][c];
+                }
+            }
+            a.sigma = m.sigma_per_cell ? m.sigma_dev : nullptr;
+            a.sigma0 = m.sigma0;
+            a.coef = m.coef_dev;
+        }
+        a.clock = g->clock;
+        a.src = g->src_dev;
+        a.nsrc = (int)g->srcs.size();
+        a.nen = 0;
+        if (r.energy) {
+            for (auto &e : g->ens) {
+                EnergyDev &d = a.en[a.nen++];
+                for (int ax = 0; ax < 3; ax++) { d.lo[ax] = (int)e.lo[ax]; d.hi[ax] = (int)e.hi[ax]; }
+                d.every = e.every;
+                d.partial = e.partial;
+            }
+        }
+        a.block_base = r.block_base;
+        const int rec = 2 * (int)(&r - &g->regions[0]);
+        Pending pe{rec, nullptr, nullptr};
+        if (g->profiling) {
+            pe.a = take_event(g);
+            pe.b = take_event(g);
+            if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
+            HIP_TRY(hipEventRecord(pe.a, g->stream));
+        }
+        HIP_TRY(launch_update_e(g->ndim, g->f64, a, kind, ng, r.pml_mask != 0, r.energy, g->stream));
+        if (g->profiling) {
+            HIP_TRY(hipEventRecord(pe.b, g->stream));
+            g->pending.push_back(pe);
+        }
+    }
+    for (auto &e : g->ens)
+        HIP_TRY(launch_energy_reduce(g->clock, e.partial, e.nslots, e.every, e.out, e.capacity, g->stream));
+    for (auto &r : g->regions) {
+        HArgs a{};
+        for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
+        fill_fields(g, a.n, a.per);
+        for (int ax = 0; ax < 3; ax++) { a.lo[ax] = r.lo[ax]; a.ext[ax] = r.hi[ax] - r.lo[ax]; }
+        a.ext12 = a.ext[1] * a.ext[2];
+        a.dt = g->dt;
+        for (int c = 0; c < 3; c++)
+            for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiH[c][t];
+        for (int ax = 0; ax < 3; ax++) { a.pml_b[ax] = g->pml_bh[ax]; a.pml_c[ax] = g->pml_ch[ax]; }
+        const int rec = 2 * (int)(&r - &g->regions[0]) + 1;
+        Pending pe{rec, nullptr, nullptr};
+        if (g->profiling) {
+            pe.a = take_event(g);
+            pe.b = take_event(g);
+            if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
+            HIP_TRY(hipEventRecord(pe.a, g->stream));
+        }
+        HIP_TRY(launch_update_h(g->ndim, g->f64, a, r.pml_mask != 0, g->stream));
+        if (g->profiling) {
+            HIP_TRY(hipEventRecord(pe.b, g->stream));
+            g->pending.push_back(pe);
+        }
+    }
+    for (auto &d : g->dfts) {
+        DftArgs a{};
+        a.axis = d.axis;
+        a.npts = d.npts;
+        for (int ax = 0; ax < 3; ax++) { a.lo[ax] = (int)d.lo[ax]; a.ext[ax] = (int)(d.hi[ax] - d.lo[ax]); }
+        a.ext12 = a.ext[1] * a.ext[2];
+        fill_fields(g, a.n, a.per);
+        a.E[0] = g->E[d.t1]; a.E[1] = g->E[d.t2];
+        a.H[0] = g->H[d.t1]; a.H[1] = g->H[d.t2];
+        a.stage = d.stage;
+        a.slot = d.nstaged;
+        HIP_TRY(launch_dft_stage(g->f64, a, g->stream));
+        d.nstaged++;
+        if (d.nstaged == kDftSlots) TRY(flush_dft(g, d));
+    }
+    g->steps++;
+    return FDTDB_OK;
+}
+
+fdtdb_status sync(fdtdb_grid_s *g) {
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return FDTDB_OK;
+}
+
+fdtdb_status flush_all(fdtdb_grid_s *g) {
+    for (auto &d : g->dfts) TRY(flush_dft(g, d));
+    return FDTDB_OK;
+}
+
+// copy a device array of the storage type to host doubles
+fdtdb_status read_state(fdtdb_grid_s *g, const void *src, long long n, double *out) {
+    if (!src) {
+        std::fill(out, out + n, 0.0);
+        return FDTDB_OK;
+    }
+    if (g->f64) {
+        HIP_TRY(hipMemcpy(out, src, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp((size_t)n);
+        HIP_TRY(hipMemcpy(tmp.data(), src, 4 * (size_t)n, hipMemcpyDeviceToHost));
+        for (long long i = 0; i < n; i++) out[i] = tmp[i];
+    }
+    return FDTDB_OK;
+}
+
+fdtdb_status write_state(fdtdb_grid_s *g, void *dst, long long n, const double *in) {
+    if (g->f64) {
+        HIP_TRY(hipMemcpy(dst, in, 8 * (size_t)n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> tmp((size_t)n);
+        for (long long i = 0; i < n; i++) tmp[i] = (float)in[i];
+        HIP_TRY(hipMemcpy(dst, tmp.data(), 4 * (size_t)n, hipMemcpyHostToDevice));
+    }
+    return FDTDB_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char *fdtdb_last_error(void) { return g_err.c_str(); }
+const char *fdtdb_version(void) { return "fdtdb 0.1 (gfx950)"; }
+
+fdtdb_status fdtdb_create_grid(const fdtdb_grid_desc *d, fdtdb_grid *out) {
+    if (!d || !out) return fail(FDTDB_E_INVALID, "null argument");
+    *out = nullptr;
+    if (d->ndim < 1 || d->ndim > 3) return fail(FDTDB_E_INVALID, "ndim must be 1, 2 or 3");
+    if (!(d->courant > 0.0)) return fail(FDTDB_E_INVALID, "courant must be > 0");
+    if (d->courant > 1.0 / std::sqrt((double)d->ndim) + 1e-15)
+        return fail(FDTDB_E_UNSTABLE, "courant %.6g exceeds the vacuum limit 1/sqrt(%d)", d->courant, d->ndim);
+    if (d->dtype != FDTDB_F32 && d->dtype != FDTDB_F64) return fail(FDTDB_E_INVALID, "bad dtype");
+    long long total = 1;
+    for (int a = 0; a < 3; a++) {
+        long long na = a < d->ndim ? d->n[a] : 1;
+        if (na < 1 || na > (1 << 30)) return fail(FDTDB_E_INVALID, "bad extent on axis %d", a);
+        total *= na;
+    }
+    if (total >= (1LL << 31)) return fail(FDTDB_E_INVALID, "grid too large (%lld cells)", total);
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(FDTDB_E_DEVICE, "no HIP device: %s", hipGetErrorString(he));
+    auto *g = new fdtdb_grid_s();
+    g->ndim = d->ndim;
+    for (int a = 0; a < 3; a++) {
+        g->n[a] = a < d->ndim ? (int)d->n[a] : 1;
+        g->bc[a] = a < d->ndim ? (int)d->bc[a] : FDTDB_BC_PERIODIC;
+        if (g->bc[a] < 0 || g->bc[a] > 2) { delete g; return fail(FDTDB_E_INVALID, "bad boundary on axis %d", a); }
+        g->pml[a] = g->bc[a] == FDTDB_BC_PML ? d->pml_cells[a] : 0;
+        if (g->bc[a] == FDTDB_BC_PML && (g->pml[a] < 1 || 2 * g->pml[a] >= g->n[a])) {
+            delete g;
+            return fail(FDTDB_E_INVALID, "bad CPML thickness on axis %d", a);
+        }
+    }
+    g->ncell = total;
+    g->dt = d->courant;
+    g->R0 = d->pml_R0 > 0 ? d->pml_R0 : 1e-8;
+    g->f64 = d->dtype == FDTDB_F64;
+    if (d->hip_stream) {
+        g->stream = (hipStream_t)d->hip_stream;
+    } else {
+        he = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+        if (he != hipSuccess) { delete g; return fail(FDTDB_E_DEVICE, "stream: %s", hipGetErrorString(he)); }
+        g->own_stream = true;
+    }
+    fdtdb_status st = FDTDB_OK;
+    for (int c = 0; c < 3 && st == FDTDB_OK; c++) {
+        if (e_active(g->ndim, c)) st = g->alloc(&g->E[c], words(total, g->f64));
+        if (st == FDTDB_OK && h_active(g->ndim, c)) st = g->alloc(&g->H[c], words(total, g->f64));
+    }
+    if (st == FDTDB_OK) st = g->alloc((void **)&g->clock, sizeof(Clock));
+    if (st == FDTDB_OK) st = g->alloc((void **)&g->flag_dev, sizeof(int));
+    if (st != FDTDB_OK) {
+        std::string msg = g_err;
+        fdtdb_destroy_grid(g);
+        g_err = msg;
+        return st;
+    }
+    *out = g;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_destroy_grid(fdtdb_grid g) {
+    if (!g) return FDTDB_OK;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    for (auto &p : g->pending) { g->pool.push_back(p.a); g->pool.push_back(p.b); }
+    for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
+    for (void *p : g->allocs) (void)hipFree(p);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_eps_inf(fdtdb_grid g, const fdtdb_box *box, double eps_inf, int *material_id) {
+    TRY(check_new_material(g, box, false));
+    if (!(eps_inf > 0.0) || !std::isfinite(eps_inf)) return fail(FDTDB_E_INVALID, "eps_inf must be > 0");
+    Material &m = new_material(g, box, K_BACKGROUND);
+    m.eps = eps_inf;
+    if (material_id) *material_id = (int)g->mats.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_drude(fdtdb_grid g, const fdtdb_box *box, double omega_p, double gamma, double eps_inf,
+                             int *material_id) {
+    TRY(check_new_material(g, box, true));
+    if (!(eps_inf > 0.0) || !(omega_p >= 0.0) || !(gamma >= 0.0))
+        return fail(FDTDB_E_INVALID, "Drude needs eps_inf > 0, omega_p >= 0, gamma >= 0");
+    const double dt = g->dt;
+    // lossless lattice bound: eps 4/dt^2 - wp^2 - 4 ndim >= 0
+    const double margin = eps_inf * 4.0 / (dt * dt) - omega_p * omega_p - 4.0 * g->ndim;
+    if (margin < 0.0)
+        return fail(FDTDB_E_UNSTABLE, "Drude medium unstable: need eps_inf >= %.6g", dt * dt * (omega_p * omega_p + 4.0 * g->ndim) / 4.0);
+    Material &m = new_material(g, box, K_DRUDE);
+    m.eps = eps_inf;
+    m.omega0 = omega_p;
+    m.gamma0 = gamma;
+    const double gg = 0.5 * gamma * dt;
+    m.coef.assign(kCoefHead, 0.0);
+    m.coef[0] = omega_p * omega_p * dt * dt / (1.0 + gg);
+    m.coef[1] = (1.0 - gg) / (1.0 + gg);
+    m.coef[2] = omega_p > 0 ? 1.0 / (omega_p * omega_p) : 0.0;
+    TRY(g->alloc((void **)&m.coef_dev, 8 * m.coef.size()));
+    HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
+    for (int c = 0; c < 3; c++)
+        if (e_active(g->ndim, c)) TRY(g->alloc(&m.P[0][c], words(m.mcells, g->f64)));
+    if (material_id) *material_id = (int)g->mats.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double omega0, double gamma0,
+                                    double eps_inf, const double *sigma_cells, double sigma_uniform, int n_bath,
+                                    const double *omega_j, const double *gamma_j, const double *k_j,
+                                    int *material_id) {
+    TRY(check_new_material(g, box, true));
+    if (!(eps_inf > 0.0) || !(omega0 > 0.0) || !(gamma0 >= 0.0) || n_bath < 0 || n_bath > 64)
+        return fail(FDTDB_E_INVALID, "Lorentz-Bath needs eps_inf > 0, omega0 > 0, gamma0 >= 0, 0 <= n_bath <= 64");
+    if (n_bath > 0 && (!omega_j || !gamma_j || !k_j)) return fail(FDTDB_E_INVALID, "bath arrays missing");
+    const double dt = g->dt;
+    long long mc = 1;
+    for (int a = 0; a < 3; a++) mc *= box->hi[a] - box->lo[a];
+    double smax = sigma_uniform;
+    if (sigma_cells) {
+        smax = 0.0;
+        for (long long q = 0; q < mc; q++) {
+            if (!(sigma_cells[q] > 0.0) || !std::isfinite(sigma_cells[q]))
+                return fail(FDTDB_E_INVALID, "sigma must be > 0 in every cell");
+            smax = std::max(smax, sigma_cells[q]);
+        }
+    } else if (!(sigma_uniform > 0.0)) {
+        return fail(FDTDB_E_INVALID, "sigma must be > 0");
+    }
+    if (omega0 * dt >= 2.0) return fail(FDTDB_E_UNSTABLE, "omega0 dt >= 2");
+    const double w02 = omega0 * omega0;
+    const double margin = eps_inf * (4.0 / (dt * dt) - w02) - w02 * smax - 4.0 * g->ndim * (1.0 - w02 * dt * dt / 4.0);
+    if (margin < 0.0) return fail(FDTDB_E_UNSTABLE, "Lorentz medium violates the lattice stability bound (margin %.6g)", margin);
+    for (int jb = 0; jb < n_bath; jb++) {
+        if (!(omega_j[jb] > 0.0) || omega_j[jb] * dt >= 2.0 || !(gamma_j[jb] >= 0.0) || !std::isfinite(k_j[jb]))
+            return fail(FDTDB_E_UNSTABLE, "bath mode %d: need 0 < omega_j dt < 2, gamma_j >= 0", jb);
+    }
+    Material &m = new_material(g, box, K_BATH);
+    m.eps = eps_inf;
+    m.omega0 = omega0;
+    m.gamma0 = gamma0;
+    m.sigma0 = sigma_uniform;
+    m.sigma_max = smax;
+    m.nb = n_bath;
+    // groups of four modes; pad to a supported count with uncoupled modes (k = 0 keeps them at zero)
+    int ng = (n_bath + 3) / 4;
+    static const int supported[] = {0, 1, 2, 3, 4, 6, 8, 12, 16};
+    for (int s : supported)
+        if (s >= ng) { ng = s; break; }
+    m.ng = ng;
+    m.wj.assign(omega_j, omega_j + n_bath);
+    m.gj.assign(gamma_j, gamma_j + n_bath);
+    m.kj.assign(k_j, k_j + n_bath);
+    // coefficient table (FP64): eq:Pz_update-LB and eq:Yzj_finite_difference
+    double skc = 0.0;
+    std::vector<double> aj(4 * ng, 0.0), bj(4 * ng, 0.0), cj(4 * ng, 0.0), kk(4 * ng, 0.0), w2(4 * ng, 0.0);
+    for (int jb = 0; jb < n_bath; jb++) {
+        const double den = 1.0 + 0.5 * gamma_j[jb] * dt;
+        aj[jb] = (2.0 - omega_j[jb] * omega_j[jb] * dt * dt) / den;
+        bj[jb] = -2.0 / den;
+        cj[jb] = k_j[jb] * dt / (2.0 * den);
+        kk[jb] = k_j[jb];
+        w2[jb] = omega_j[jb] * omega_j[jb];
+        skc += k_j[jb] * cj[jb];
+    }
+    const double A = 1.0 + 0.5 * gamma0 * dt + 0.5 * dt * skc;
+    m.coef.assign(kCoefHead + kCoefMode * 4 * ng, 0.0);
+    m.coef[0] = w02 * dt * dt / A;
+    m.coef[1] = (w02 * dt * dt - 2.0) / A;
+    m.coef[2] = (1.0 - 0.5 * gamma0 * dt - 0.5 * dt * skc) / A;
+    m.coef[3] = 1.0 / w02;
+    m.coef[4] = w02;
+    for (int jb = 0; jb < 4 * ng; jb++) {
+        double *md = &m.coef[kCoefHead + kCoefMode * jb];
+        md[0] = jb < n_bath ? aj[jb] : 0.0;
+        md[1] = jb < n_bath ? bj[jb] + 1.0 : 0.0;
+        md[2] = cj[jb];
+        md[3] = 0.5 * dt * kk[jb] * aj[jb] / A;
+        md[4] = 0.5 * dt * kk[jb] * bj[jb] / A;
+        md[5] = w2[jb];
+    }
+    TRY(g->alloc((void **)&m.coef_dev, 8 * m.coef.size()));
+    HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
+    if (sigma_cells) {
+        m.sigma_per_cell = true;
+        TRY(g->alloc(&m.sigma_dev, words(mc, g->f64)));
+        TRY(write_state(g, m.sigma_dev, mc, sigma_cells));
+    }
+    for (int lvl = 0; lvl < 2; lvl++)
+        for (int c = 0; c < 3; c++) {
+            if (!e_active(g->ndim, c)) continue;
+            TRY(g->alloc(&m.P[lvl][c], words(mc, g->f64)));
+            if (ng) TRY(g->alloc(&m.Y[lvl][c], words(mc * 4 * ng, g->f64)));
+        }
+    if (material_id) *material_id = (int)g->mats.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_bath_params(int form, double omega0, double gamma0, int n_bath, double width, double bath_gamma,
+                               double dephasing, double *omega_j, double *gamma_j, double *k_j) {
+    if (n_bath < 2 || !omega_j || !gamma_j || !k_j || form < 0 || form > 2 || !(width > 0.0))
+        return fail(FDTDB_E_INVALID, "bath_params: need n_bath >= 2, width > 0, form in {0,1,2}");
+    const double dw = width / (n_bath - 1);
+    const double kb = std::sqrt(2.0 * dw / M_PI * dephasing);
+    const double G = gamma0 + dephasing;
+    for (int jb = 0; jb < n_bath; jb++) {
+        const double w = omega0 - width / 2 + width * jb / (n_bath - 1);
+        omega_j[jb] = w;
+        gamma_j[jb] = bath_gamma;
+        const double d = w - omega0;
+        if (form == 0) k_j[jb] = kb;
+        else if (form == 1) k_j[jb] = kb * std::sqrt(G * G / (G * G + d * d));
+        else k_j[jb] = kb * std::exp(-d * d / (4.0 * G * G));
+    }
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_add_source(fdtdb_grid g, int component, const fdtdb_box *box, double omega_c, double width,
+                              double amplitude, const double *profile, int *source_id) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "sources must be added before the first step");
+    if (!box_ok(g, box)) return fail(FDTDB_E_INVALID, "source box outside the grid");
+    if (component < 0 || component > 2 || !e_active(g->ndim, component))
+        return fail(FDTDB_E_INVALID, "source component not carried by a %dD grid", g->ndim);
+    if (!(width > 0.0)) return fail(FDTDB_E_INVALID, "width must be > 0");
+    if ((int)g->srcs.size() >= kMaxSources) return fail(FDTDB_E_INVALID, "at most %d sources", kMaxSources);
+    // the box must sit in one eps_inf
+    double eps = -1.0;
+    for (int64_t i = box->lo[0]; i < box->hi[0]; i++)
+        for (int64_t j = box->lo[1]; j < box->hi[1]; j++)
+            for (int64_t k = box->lo[2]; k < box->hi[2]; k++) {
+                double e = 1.0;
+                for (auto &m : g->mats)
+                    if (i >= m.lo[0] && i < m.hi[0] && j >= m.lo[1] && j < m.hi[1] && k >= m.lo[2] && k < m.hi[2]) e = m.eps;
+                if (eps < 0) eps = e;
+                else if (e != eps) return fail(FDTDB_E_INVALID, "source box spans several eps_inf values");
+            }
+    Source s;
+    s.comp = component;
+    for (int a = 0; a < 3; a++) { s.lo[a] = box->lo[a]; s.hi[a] = box->hi[a]; }
+    s.omega_c = omega_c;
+    s.width = width;
+    s.amplitude = amplitude;
+    s.eps = eps;
+    if (profile) {
+        long long nc = 1;
+        for (int a = 0; a < 3; a++) nc *= box->hi[a] - box->lo[a];
+        s.profile.assign(profile, profile + nc);
+    }
+    g->srcs.push_back(std::move(s));
+    if (source_id) *source_id = (int)g->srcs.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_add_dft_flux(fdtdb_grid g, int axis, const fdtdb_box *plane, int nfreq, const double *omega,
+                                int *monitor_id) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "monitors must be added before the first step");
+    if (axis < 0 || axis >= g->ndim) return fail(FDTDB_E_INVALID, "bad axis");
+    if (!box_ok(g, plane) || plane->hi[axis] != plane->lo[axis] + 1)
+        return fail(FDTDB_E_INVALID, "flux plane must be inside the grid and one cell thick along its axis");
+    if (nfreq < 1 || !omega) return fail(FDTDB_E_INVALID, "need frequencies");
+    Dft d;
+    d.axis = axis;
+    d.npts = 1;
+    for (int a = 0; a < 3; a++) {
+        d.lo[a] = plane->lo[a];
+        d.hi[a] = plane->hi[a];
+        d.npts *= (int)(plane->hi[a] - plane->lo[a]);
+    }
+    d.nf = nfreq;
+    d.t1 = curl_a1(axis);
+    d.t2 = curl_a2(axis);
+    d.omega.assign(omega, omega + nfreq);
+    TRY(g->alloc((void **)&d.omega_dev, 8 * (size_t)nfreq));
+    HIP_TRY(hipMemcpy(d.omega_dev, omega, 8 * (size_t)nfreq, hipMemcpyHostToDevice));
+    TRY(g->alloc((void **)&d.stage, 8 * (size_t)kDftSlots * 4 * d.npts));
+    TRY(g->alloc((void **)&d.tw, 32 * (size_t)kDftSlots * nfreq));
+    TRY(g->alloc((void **)&d.acc, 16 * (size_t)4 * nfreq * d.npts));
+    TRY(g->alloc((void **)&d.flux_dev, 8 * (size_t)nfreq));
+    g->dfts.push_back(std::move(d));
+    if (monitor_id) *monitor_id = (int)g->dfts.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int every, int *monitor_id) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "monitors must be added before the first step");
+    if (!box_ok(g, box) || every < 1) return fail(FDTDB_E_INVALID, "bad energy box or period");
+    if (in_pml(g, box->lo, box->hi)) return fail(FDTDB_E_INVALID, "energy box overlaps the CPML layer");
+    if ((int)g->ens.size() >= kMaxEnergy) return fail(FDTDB_E_INVALID, "at most %d energy monitors", kMaxEnergy);
+    Energy e;
+    for (int a = 0; a < 3; a++) { e.lo[a] = box->lo[a]; e.hi[a] = box->hi[a]; }
+    e.every = every;
+    g->ens.push_back(e);
+    if (monitor_id) *monitor_id = (int)g->ens.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (chunk_steps < 0) return fail(FDTDB_E_INVALID, "chunk must be >= 0");
+    if (g->graph) { (void)hipGraphExecDestroy(g->graph); g->graph = nullptr; }
+    int c = chunk_steps;
+    if (c > 0) {
+        if (!g->dfts.empty()) c = ((c + kDftSlots - 1) / kDftSlots) * kDftSlots;
+        c += c & 1;
+    }
+    g->graph_chunk = c;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (nsteps < 0) return fail(FDTDB_E_INVALID, "nsteps < 0");
+    TRY(finalize(g));
+    TRY(ensure_energy_capacity(g, g->steps + nsteps));
+    int64_t left = nsteps;
+    while (left > 0) {
+        bool aligned = true;
+        for (auto &d : g->dfts) aligned = aligned && d.nstaged == 0;
+        const int chunk = g->graph_chunk;
+        if (chunk > 0 && !g->profiling && left >= chunk && aligned && (g->steps & 1) == 0) {
+            if (!g->graph) {
+                hipGraph_t graph;
+                HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+                const long long s0 = g->steps;
+                fdtdb_status st = FDTDB_OK;
+                for (int s = 0; s < chunk && st == FDTDB_OK; s++) st = enqueue_step(g);
+                hipError_t ce = hipStreamEndCapture(g->stream, &graph);
+                g->steps = s0;   // the captured steps run below, at replay
+                if (st != FDTDB_OK) return st;
+                if (ce != hipSuccess) return fail(FDTDB_E_DEVICE, "graph capture: %s", hipGetErrorString(ce));
+                HIP_TRY(hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0));
+                (void)hipGraphDestroy(graph);
+            }
+            HIP_TRY(hipGraphLaunch(g->graph, g->stream));
+            g->steps += chunk;
+            left -= chunk;
+        } else {
+            TRY(enqueue_step(g));
+            left -= 1;
+        }
+    }
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps) {
+    if (!g || !steps) return fail(FDTDB_E_INVALID, "null argument");
+    *steps = g->steps;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_synchronize(fdtdb_grid g) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    HIP_TRY(hipMemsetAsync(g->flag_dev, 0, sizeof(int), g->stream));
+    for (int c = 0; c < 3; c++) {
+        if (g->E[c]) HIP_TRY(launch_nonfinite(g->f64, g->E[c], g->ncell, g->flag_dev, g->stream));
+        if (g->H[c]) HIP_TRY(launch_nonfinite(g->f64, g->H[c], g->ncell, g->flag_dev, g->stream));
+    }
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, g->flag_dev, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    if (flag) return fail(FDTDB_E_DIVERGED, "non-finite field after %lld steps", (long long)g->steps);
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int id, double *flux, double *raw) {
+    if (!g || id < 0 || id >= (int)g->dfts.size() || !flux) return fail(FDTDB_E_INVALID, "bad monitor");
+    Dft &d = g->dfts[id];
+    if (g->finalized) TRY(flush_dft(g, d));
+    if (g->finalized) HIP_TRY(launch_dft_flux(d.acc, d.npts, d.nf, d.flux_dev, g->stream));
+    TRY(sync(g));
+    HIP_TRY(hipMemcpy(flux, d.flux_dev, 8 * (size_t)d.nf, hipMemcpyDeviceToHost));
+    if (raw) {
+        // device layout [field][f][p] -> ABI layout [field][p][f]
+        std::vector<double2> tmp((size_t)4 * d.nf * d.npts);
+        HIP_TRY(hipMemcpy(tmp.data(), d.acc, 16 * tmp.size(), hipMemcpyDeviceToHost));
+        for (int fld = 0; fld < 4; fld++)
+            for (int f = 0; f < d.nf; f++)
+                for (int p = 0; p < d.npts; p++) {
+                    const double2 v = tmp[((size_t)fld * d.nf + f) * d.npts + p];
+                    double *o = raw + (((size_t)fld * d.npts + p) * d.nf + f) * 2;
+                    o[0] = v.x;
+                    o[1] = v.y;
+                }
+    }
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_energy(fdtdb_grid g, int id, double *out, int64_t capacity, int64_t *n_samples) {
+    if (!g || id < 0 || id >= (int)g->ens.size()) return fail(FDTDB_E_INVALID, "bad monitor");
+    Energy &e = g->ens[id];
+    TRY(sync(g));
+    const long long n = g->steps == 0 ? 0 : (g->steps - 1) / e.every + 1;
+    if (n_samples) *n_samples = n;
+    const long long m = std::min<long long>(n, capacity);
+    if (out && m > 0) HIP_TRY(hipMemcpy(out, e.out, 24 * (size_t)m, hipMemcpyDeviceToHost));
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, double *out) {
+    if (!g || !out || component < 0 || component > 5) return fail(FDTDB_E_INVALID, "bad component");
+    TRY(sync(g));
+    const void *src = component < 3 ? g->E[component] : g->H[component - 3];
+    return read_state(g, src, g->ncell, out);
+}
+
+fdtdb_status fdtdb_set_field(fdtdb_grid g, int component, const double *in) {
+    if (!g || !in || component < 0 || component > 5) return fail(FDTDB_E_INVALID, "bad component");
+    void *dst = component < 3 ? g->E[component] : g->H[component - 3];
+    if (!dst) return fail(FDTDB_E_INVALID, "component not carried by this grid");
+    TRY(sync(g));
+    return write_state(g, dst, g->ncell, in);
+}
+
+fdtdb_status fdtdb_get_polarization(fdtdb_grid g, int mid, int c, int level, double *out) {
+    if (!g || mid < 0 || mid >= (int)g->mats.size() || c < 0 || c > 2 || level < 0 || level > 1 || !out)
+        return fail(FDTDB_E_INVALID, "bad argument");
+    Material &m = g->mats[mid];
+    if (m.kind == K_BACKGROUND || !e_active(g->ndim, c)) return fail(FDTDB_E_INVALID, "no polarization");
+    TRY(sync(g));
+    if (m.kind == K_DRUDE) {
+        if (level == 1) {
+            std::fill(out, out + m.mcells, 0.0);
+            return FDTDB_OK;
+        }
+        return read_state(g, m.P[0][c], m.mcells, out);
+    }
+    const int slot = (int)((g->steps + level) & 1);
+    return read_state(g, m.P[slot][c], m.mcells, out);
+}
+
+fdtdb_status fdtdb_get_bath(fdtdb_grid g, int mid, int c, int level, double *out) {
+    if (!g || mid < 0 || mid >= (int)g->mats.size() || c < 0 || c > 2 || level < 0 || level > 1 || !out)
+        return fail(FDTDB_E_INVALID, "bad argument");
+    Material &m = g->mats[mid];
+    if (m.kind != K_BATH || m.nb == 0 || !e_active(g->ndim, c)) return fail(FDTDB_E_INVALID, "no bath");
+    TRY(sync(g));
+    const int slot = (int)((g->steps + level) & 1);
+    std::vector<double> tmp((size_t)m.mcells * 4 * m.ng);
+    TRY(read_state(g, m.Y[slot][c], (long long)tmp.size(), tmp.data()));
+    // device layout [group][cell][4] -> [mode][cell]
+    for (int jb = 0; jb < m.nb; jb++)
+        for (long long q = 0; q < m.mcells; q++) out[(size_t)jb * m.mcells + q] = tmp[((size_t)(jb / 4) * m.mcells + q) * 4 + (jb & 3)];
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out) {
+    if (!g || !out) return fail(FDTDB_E_INVALID, "null argument");
+    TRY(finalize(g));
+    fdtdb_stats s{};
+    s.cells = g->ncell;
+    double be = 0.0, bh = 0.0;
+    for (auto &r : g->regions) {
+        double e, h;
+        region_bytes(g, r, &e, &h);
+        be += e * (double)r.cells();
+        bh += h * (double)r.cells();
+        if (r.mat >= 0 && g->mats[r.mat].kind != K_BACKGROUND) {
+            s.dispersive_cells += r.cells();
+            if (g->mats[r.mat].nb) s.bath_cells += r.cells();
+        }
+    }
+    s.bytes_per_step_e = be;
+    s.bytes_per_step_h = bh;
+    s.bytes_per_step = be + bh;
+    s.launches_per_step = g->launches_per_step;
+    *out = s;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_profiling(fdtdb_grid g, int on) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    g->profiling = on != 0;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_kernel_records(fdtdb_grid g, fdtdb_kernel_record *out, int capacity, int *count) {
+    if (!g || !count) return fail(FDTDB_E_INVALID, "null argument");
+    TRY(finalize(g));
+    TRY(collect_events(g));
+    *count = (int)g->records.size();
+    if (out)
+        for (int i = 0; i < std::min(capacity, (int)g->records.size()); i++) out[i] = g->records[i];
+    return FDTDB_OK;
+}
+
+}  // extern "C"

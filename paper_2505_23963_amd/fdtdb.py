@@ -1,0 +1,265 @@
+"""ctypes binding of libfdtdb (the C-ABI declared in include/fdtdb.h).
+
+Argument marshalling only: every step of the time-stepping path runs in the
+library's HIP kernels.  The binding refuses to run without the built
+library; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtdb.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSTABLE, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+BC_PML, BC_PERIODIC, BC_CLOSED = 0, 1, 2
+_FORMS = {"uniform": 0, "lorentzian": 1, "gaussian": 2}
+
+
+class FdtdbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fdtdb status {status}: {msg}")
+        self.status = status
+
+
+class Box(C.Structure):
+    _fields_ = [("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int64 * 3), ("courant", C.c_double), ("dtype", C.c_int),
+                ("bc", C.c_int * 3), ("pml_cells", C.c_int * 3), ("pml_R0", C.c_double),
+                ("hip_stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("dispersive_cells", C.c_int64), ("bath_cells", C.c_int64),
+                ("bytes_per_step", C.c_double), ("bytes_per_step_e", C.c_double), ("bytes_per_step_h", C.c_double),
+                ("launches_per_step", C.c_int)]
+
+
+class KernelRecord(C.Structure):
+    _fields_ = [("region", C.c_int), ("phase", C.c_int), ("kind", C.c_int), ("n_bath", C.c_int), ("pml", C.c_int),
+                ("cells", C.c_int64), ("bytes", C.c_double), ("ms_total", C.c_double), ("launches", C.c_int64)]
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+
+# (name, restype, argtypes) of every entry point of include/fdtdb.h
+SIGNATURES = [
+    ("fdtdb_create_grid", C.c_int, [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]),
+    ("fdtdb_destroy_grid", C.c_int, [C.c_void_p]),
+    ("fdtdb_set_eps_inf", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.POINTER(C.c_int)]),
+    ("fdtdb_set_drude", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
+    ("fdtdb_set_lorentz_bath", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
+                                         C.c_double, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]),
+    ("fdtdb_bath_params", C.c_int, [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
+                                    _dp, _dp, _dp]),
+    ("fdtdb_add_source", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
+                                   C.POINTER(C.c_int)]),
+    ("fdtdb_add_dft_flux", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_int, _dp, C.POINTER(C.c_int)]),
+    ("fdtdb_add_energy_monitor", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_int, C.POINTER(C.c_int)]),
+    ("fdtdb_step", C.c_int, [C.c_void_p, C.c_int64]),
+    ("fdtdb_synchronize", C.c_int, [C.c_void_p]),
+    ("fdtdb_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("fdtdb_set_graph", C.c_int, [C.c_void_p, C.c_int]),
+    ("fdtdb_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp, _dp]),
+    ("fdtdb_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
+    ("fdtdb_get_field", C.c_int, [C.c_void_p, C.c_int, _dp]),
+    ("fdtdb_set_field", C.c_int, [C.c_void_p, C.c_int, _dp]),
+    ("fdtdb_get_polarization", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]),
+    ("fdtdb_get_bath", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]),
+    ("fdtdb_get_stats", C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    ("fdtdb_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
+    ("fdtdb_kernel_records", C.c_int, [C.c_void_p, C.POINTER(KernelRecord), C.c_int, C.POINTER(C.c_int)]),
+    ("fdtdb_last_error", C.c_char_p, []),
+    ("fdtdb_version", C.c_char_p, []),
+]
+
+
+def lib():
+    """Load libfdtdb.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2505_23963_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise FdtdbError(st, lib().fdtdb_last_error().decode())
+
+
+def _box(b) -> Box:
+    x = Box()
+    for a in range(3):
+        x.lo[a] = int(b[0][a])
+        x.hi[a] = int(b[1][a])
+    return x
+
+
+def _arr(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=np.float64).ravel()
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def bath_params(form: str, omega0: float, gamma0: float, n_bath: int, width: float, bath_gamma: float,
+                dephasing: float):
+    """Table 1 map computed by the library."""
+    w, g, k = (np.zeros(n_bath) for _ in range(3))
+    _check(lib().fdtdb_bath_params(_FORMS[form], omega0, gamma0, n_bath, width, bath_gamma, dephasing,
+                                   _ptr(w), _ptr(g), _ptr(k)))
+    return w, g, k
+
+
+class Grid:
+    """A device grid built from an fdtdb_inputs Problem description."""
+
+    def __init__(self, problem, stream: Optional[int] = None, graph_chunk: int = 0, dtype: Optional[str] = None):
+        L = lib()
+        self.p = problem
+        d = GridDesc()
+        d.ndim = problem.ndim
+        for a in range(3):
+            d.n[a] = int(problem.n[a])
+            d.bc[a] = int(problem.bc[a])
+            d.pml_cells[a] = int(problem.pml_cells[a])
+        d.courant = problem.courant
+        dt = dtype or problem.dtype
+        d.dtype = F64 if dt == "f64" else F32
+        d.pml_R0 = problem.pml_R0
+        d.hip_stream = stream
+        h = C.c_void_p()
+        _check(L.fdtdb_create_grid(C.byref(d), C.byref(h)))
+        self.h = h
+        self.mat_ids = []
+        for m in problem.materials:
+            kind = type(m).__name__
+            mid = C.c_int(-1)
+            b = _box(m.box)
+            if kind == "Dielectric":
+                _check(L.fdtdb_set_eps_inf(self.h, C.byref(b), m.eps_inf, C.byref(mid)))
+            elif kind == "Drude":
+                _check(L.fdtdb_set_drude(self.h, C.byref(b), m.omega_p, m.gamma, m.eps_inf, C.byref(mid)))
+            elif kind == "LorentzBath":
+                if m.n_bath and m.form is not None:
+                    wj, gj, kj = bath_params(m.form, m.omega0, m.gamma0, m.n_bath, m.width, m.bath_gamma,
+                                             m.dephasing)
+                else:
+                    wj, gj, kj = _arr(m.omega_j), _arr(m.gamma_j), _arr(m.k_j)
+                sig = _arr(m.sigma_cells)
+                _check(L.fdtdb_set_lorentz_bath(self.h, C.byref(b), m.omega0, m.gamma0, m.eps_inf, _ptr(sig),
+                                                m.sigma, m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj), C.byref(mid)))
+            else:
+                raise TypeError(kind)
+            self.mat_ids.append(mid.value)
+        for s in problem.sources:
+            prof = _arr(s.profile)
+            _check(L.fdtdb_add_source(self.h, s.comp, C.byref(_box(s.box)), s.omega_c, s.width, s.amplitude,
+                                      _ptr(prof), None))
+        for dm in problem.dfts:
+            om = _arr(dm.omega)
+            _check(L.fdtdb_add_dft_flux(self.h, dm.axis, C.byref(_box(dm.box)), len(om), _ptr(om), None))
+        for e in problem.energies:
+            _check(L.fdtdb_add_energy_monitor(self.h, C.byref(_box(e.box)), e.every, None))
+        if graph_chunk:
+            _check(L.fdtdb_set_graph(self.h, int(graph_chunk)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdtdb_destroy_grid(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        _check(lib().fdtdb_step(self.h, int(n)))
+
+    def synchronize(self):
+        _check(lib().fdtdb_synchronize(self.h))
+
+    @property
+    def steps_done(self) -> int:
+        s = C.c_int64()
+        _check(lib().fdtdb_steps_done(self.h, C.byref(s)))
+        return s.value
+
+    def field(self, comp: int) -> np.ndarray:
+        out = np.zeros(self.p.cells, np.float64)
+        _check(lib().fdtdb_get_field(self.h, comp, _ptr(out)))
+        return out.reshape(self.p.n)
+
+    def set_field(self, comp: int, values):
+        v = _arr(values)
+        _check(lib().fdtdb_set_field(self.h, comp, _ptr(v)))
+
+    def _mcells(self, mi):
+        b = self.p.materials[mi].box
+        return int(np.prod([b[1][a] - b[0][a] for a in range(3)]))
+
+    def polarization(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
+        out = np.zeros(self._mcells(mi), np.float64)
+        _check(lib().fdtdb_get_polarization(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
+        return out
+
+    def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
+        nb = self.p.materials[mi].n_bath
+        out = np.zeros(nb * self._mcells(mi), np.float64)
+        _check(lib().fdtdb_get_bath(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
+        return out.reshape(nb, -1)
+
+    def flux(self, mid: int, raw: bool = False):
+        d = self.p.dfts[mid]
+        nf = len(d.omega)
+        npts = int(np.prod([d.box[1][a] - d.box[0][a] for a in range(3)]))
+        out = np.zeros(nf, np.float64)
+        r = np.zeros(4 * npts * nf * 2, np.float64) if raw else None
+        _check(lib().fdtdb_dft_flux(self.h, mid, _ptr(out), _ptr(r)))
+        if raw:
+            rr = r.reshape(4, npts, nf, 2)
+            return out, rr[..., 0] + 1j * rr[..., 1]
+        return out
+
+    def energy(self, mid: int) -> np.ndarray:
+        n = C.c_int64()
+        _check(lib().fdtdb_energy(self.h, mid, None, 0, C.byref(n)))
+        out = np.zeros(3 * max(n.value, 1), np.float64)
+        _check(lib().fdtdb_energy(self.h, mid, _ptr(out), n.value, C.byref(n)))
+        return out[:3 * n.value].reshape(-1, 3)
+
+    def set_profiling(self, on: bool):
+        _check(lib().fdtdb_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_records(self):
+        n = C.c_int()
+        _check(lib().fdtdb_kernel_records(self.h, None, 0, C.byref(n)))
+        arr = (KernelRecord * max(n.value, 1))()
+        _check(lib().fdtdb_kernel_records(self.h, arr, n.value, C.byref(n)))
+        return [{f: getattr(arr[i], f) for f, _ in KernelRecord._fields_} for i in range(n.value)]
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().fdtdb_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}

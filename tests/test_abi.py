@@ -1,0 +1,77 @@
+"""Boundary checks that need no GPU: the library loads, exports every declared
+entry point, and its host-only Table-1 map agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdtdb.h")
+LIB = os.path.join(ROOT, "paper_2505_23963_amd", "libfdtdb.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtdb_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def libfdtdb():
+    if not os.path.exists(LIB):
+        pytest.fail("libfdtdb.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_core_api():
+    syms = declared_symbols()
+    for s in ["fdtdb_create_grid", "fdtdb_set_lorentz_bath", "fdtdb_add_source", "fdtdb_step", "fdtdb_dft_flux"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(libfdtdb):
+    missing = [s for s in declared_symbols() if not hasattr(libfdtdb, s)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    from paper_2505_23963_amd.fdtdb import SIGNATURES
+    bound = {n for n, _, _ in SIGNATURES}
+    assert set(declared_symbols()) <= bound
+
+
+@pytest.mark.parametrize("form", ["uniform", "lorentzian", "gaussian"])
+def test_bath_params_matches_oracle_table1(form):
+    """Host-only entry point: the library's Table 1 map vs the oracle's."""
+    from oracle.closed_form import table1_bath
+    from paper_2505_23963_amd import bath_params
+    args = (1.0, 0.001, 64, 0.4, 0.4 / 63 / 2, 0.02)
+    w, g, k = bath_params(form, *args)
+    w2, g2, k2 = table1_bath(form, *args)
+    assert np.allclose(w, w2, rtol=0, atol=1e-15)
+    assert np.array_equal(g, g2)
+    assert np.allclose(k, k2, rtol=1e-14, atol=0)
+
+
+def test_bath_params_rejects_bad_input():
+    from paper_2505_23963_amd import FdtdbError, bath_params
+    with pytest.raises(FdtdbError):
+        bath_params("uniform", 1.0, 0.0, 1, 0.4, 0.0, 0.02)
+
+
+def test_version_string(libfdtdb):
+    libfdtdb.fdtdb_version.restype = ctypes.c_char_p
+    assert b"gfx950" in libfdtdb.fdtdb_version()
+
+
+def test_product_never_imports_oracle():
+    """The product path (package + inputs) must not reach the oracle."""
+    for d in ["paper_2505_23963_amd", "fdtdb_inputs"]:
+        for dirpath, _, files in os.walk(os.path.join(ROOT, d)):
+            for f in files:
+                if f.endswith((".py", ".hip", ".h", ".cpp")):
+                    txt = open(os.path.join(dirpath, f)).read()
+                    assert "import oracle" not in txt and "from oracle" not in txt, f
+                    assert "fdtd_oracle" not in txt, f

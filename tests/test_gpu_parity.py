@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the same seeded inputs.
+
+Bars: FP64 state <= 1e-12 relative L2, FP32 state <= 1e-5 relative L2 (the
+FP32-state target of the method's precision policy), DFT spectra in FP64.
+"""
+import numpy as np
+import pytest
+
+from fdtdb_inputs import configs
+from fdtdb_inputs.problem import (CLOSED, PERIODIC, PML, DftFlux, Drude, EnergyMonitor, LorentzBath, Problem,
+                                  Source, box)
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rel_fields(g, o, comps):
+    """Per-component relative L2, with components far below the largest one measured against
+    1e-6 of the largest norm (a field that is zero by symmetry has no relative error)."""
+    ref = {c: o.field(c) for c in comps}
+    big = max(np.linalg.norm(v) for v in ref.values())
+    return {c: np.linalg.norm(g.field(c) - ref[c]) / max(np.linalg.norm(ref[c]), 1e-6 * big) for c in comps}
+
+
+def run_pair(oracle_lib, p, steps=None, graph=0, dtype=None):
+    from paper_2505_23963_amd import Grid
+    n = p.steps if steps is None else steps
+    print(f"[gpu] {p.name} n={p.n} steps={n} dtype={dtype or p.dtype} graph={graph}", flush=True)
+    g = Grid(p, graph_chunk=graph, dtype=dtype)
+    g.step(n)
+    g.synchronize()
+    o = oracle_lib.run(p, steps=n)
+    return g, o
+
+
+def fields_of(p):
+    from fdtdb_inputs.problem import active_components
+    e, h = active_components(p.ndim)
+    return list(e) + list(h)
+
+
+# ------------------------------------------------------------------------------------------ 1D
+def test_config1_fp64_full(oracle_lib):
+    """The 1D Fabry-Perot workload in full (2048 cells, N_b = 16, 20000 steps), FP64."""
+    p = configs.config1_1d()
+    g, o = run_pair(oracle_lib, p, graph=64)
+    for c in fields_of(p):
+        assert rel(g.field(c), o.field(c)) < 1e-12, c
+    for mid in range(2):
+        fg, fo = g.flux(mid), o.flux(mid)
+        if mid == 0:
+            assert rel(fg, fo) < 1e-11
+        else:   # behind two opaque Drude mirrors: only compare at FP64 resolution of the inside flux
+            assert np.max(np.abs(fg - fo)) < 1e-11 * np.max(np.abs(o.flux(0)))
+    eg, eo = g.energy(0), o.energy(0)
+    assert eg.shape == eo.shape
+    assert np.max(np.abs(eg - eo)) < 1e-11 * np.abs(eo).max()
+    for lvl in (0, 1):
+        assert rel(g.polarization(1, 2, lvl), o.polarization(1, 2, lvl)) < 1e-12
+        assert rel(g.bath(1, 2, lvl), o.bath(1, 2, lvl)) < 1e-11
+
+
+def test_config1_fp32(oracle_lib):
+    p = configs.config1_1d(steps=5000, dtype="f32")
+    g, o = run_pair(oracle_lib, p)
+    for c in fields_of(p):
+        assert rel(g.field(c), o.field(c)) < 1e-5, c
+    assert rel(g.bath(1, 2, 0), o.bath(1, 2, 0)) < 1e-5
+    assert rel(g.flux(0), o.flux(0)) < 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 255, 257, 700])
+def test_1d_ragged_sizes(oracle_lib, n):
+    """Grids that are not a multiple of the block size, down to one cell."""
+    p = Problem(name=f"rag{n}", ndim=1, n=(n, 1, 1), bc=(CLOSED, PERIODIC, PERIODIC), dtype="f64", steps=300)
+    w, gm, k = configs.ohmic_bath(5, 0.8, 1.2, 1.0, seed=7)
+    if n >= 10:
+        p.materials.append(LorentzBath(box((n // 3, n - 2)), omega0=1.0, gamma0=0.01, eps_inf=1.2, sigma=0.05,
+                                       n_bath=5, omega_j=w, gamma_j=gm, k_j=k))
+        p.materials.append(Drude(box((1, 3)), omega_p=3.0, gamma=0.02, eps_inf=3.0))
+    p.sources.append(Source(comp=2, box=box((0, 1)), omega_c=1.0, width=0.5))
+    g, o = run_pair(oracle_lib, p)
+    assert rel(g.field(2), o.field(2)) < 1e-12
+    assert rel(g.field(4), o.field(4)) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------ 3D
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_config2_crop(oracle_lib, dtype, tol):
+    """3D planar-cavity layout (z: PML | vac | Drude | LB N_b=8 random sigma | Drude | vac | PML), 10 x 12 crop."""
+    p = configs.config2_3d(nx=10, ny=12, steps=220, nfreq=64, dtype=dtype)
+    g, o = run_pair(oracle_lib, p, graph=32 if dtype == "f32" else 0)
+    errs = rel_fields(g, o, range(6))
+    print("rel-L2 per component:", errs, flush=True)
+    assert max(errs.values()) < tol, errs
+    assert rel(g.flux(0), o.flux(0)) < tol
+    assert rel(g.bath(1, 0, 0), o.bath(1, 0, 0)) < tol
+
+
+def test_3d_all_components_closed_box(oracle_lib):
+    """A 3D box with closed and periodic axes, a transverse source and all six components driven."""
+    rng = np.random.default_rng(3)
+    n = (9, 7, 70)
+    p = Problem(name="box3d", ndim=3, n=n, bc=(CLOSED, PERIODIC, CLOSED), dtype="f64", steps=150)
+    w, gm, k = configs.ohmic_bath(7, 0.8, 1.2, 1.0, seed=11)
+    lb = box((1, 8), (0, 7), (20, 50))
+    p.materials += [LorentzBath(lb, omega0=1.0, gamma0=0.02, eps_inf=1.3, sigma_cells=rng.uniform(0.02, 0.1, 7 * 7 * 30),
+                                n_bath=7, omega_j=w, gamma_j=gm, k_j=k),
+                    Drude(box((0, 9), (0, 7), (55, 58)), omega_p=4.0, gamma=0.03, eps_inf=5.0)]
+    p.sources += [Source(comp=1, box=box((2, 5), (1, 3), (10, 11)), omega_c=1.0, width=0.5),
+                  Source(comp=2, box=box((4, 5), (3, 4), (12, 13)), omega_c=0.8, width=0.4, amplitude=0.7)]
+    g, o = run_pair(oracle_lib, p)
+    errs = rel_fields(g, o, range(6))
+    assert max(errs.values()) < 1e-12, errs
+
+
+# ------------------------------------------------------------------------------------------ 2D
+def test_config4_crop_explicit(oracle_lib):
+    """2D TM grid with CPML on all sides and a Lorentzian-form bath patch (N_b = 64), FP32."""
+    # compared at step 225, while the pulse is still inside the CPML-bounded domain (the field norm
+    # falls six-fold by step 400 as it leaves, inflating a relative measure of absolute rounding)
+    p = configs.config4_2d(n=160, patch=(60, 110), steps=225, nfreq=32, src_x=40, flux_x=125)
+    g, o = run_pair(oracle_lib, p)
+    for c in fields_of(p):
+        assert rel(g.field(c), o.field(c)) < 1e-5, c
+    assert rel(g.flux(0), o.flux(0)) < 1e-5
+
+
+# ------------------------------------------------------------------------------------------ properties
+def test_energy_conservation_on_gpu(oracle_lib):
+    """Lossless closed box on the GPU (FP64): the exact discrete energy stays constant."""
+    p = Problem(name="econs", ndim=2, n=(40, 30, 1), bc=(CLOSED, PERIODIC, PERIODIC), dtype="f64", steps=3000)
+    w = np.array([0.8, 0.95, 1.05, 1.2])
+    p.materials.append(LorentzBath(box((5, 35), (0, 30)), omega0=1.0, gamma0=0.0, eps_inf=1.5, sigma=0.08,
+                                   n_bath=4, omega_j=w, gamma_j=np.zeros(4), k_j=np.array([0.05, 0.1, 0.08, 0.04])))
+    p.sources.append(Source(comp=2, box=box((20, 21), (10, 20)), omega_c=1.0, width=2.0))
+    p.energies.append(EnergyMonitor(box((0, 40), (0, 30)), every=5))
+    g, o = run_pair(oracle_lib, p)
+    e = g.energy(0).sum(axis=1)
+    assert np.max(np.abs(e[4:] - e[4])) / e[4] < 1e-11
+    assert np.max(np.abs(g.energy(0) - o.energy(0))) < 1e-11 * e[4]
+
+
+def test_graph_replay_matches_direct():
+    """Graph replays (with eager work and syncs between them) equal direct launches bitwise."""
+    from paper_2505_23963_amd import Grid
+    p = configs.config2_3d(nx=6, ny=5, steps=0, nfreq=16)
+    print("[gpu] graph vs direct", flush=True)
+    a = Grid(p)
+    b = Grid(p, graph_chunk=32)
+    for rep in range(3):
+        a.step(64)
+        b.step(64)
+        a.synchronize()
+        b.synchronize()
+        for c in range(6):
+            assert np.array_equal(a.field(c), b.field(c)), (rep, c)
+    assert np.array_equal(a.flux(0), b.flux(0))
+
+
+def test_rerun_bitwise_identical():
+    from paper_2505_23963_amd import Grid
+    p = configs.config2_3d(nx=6, ny=5, steps=100, nfreq=16)
+    out = []
+    for _ in range(2):
+        g = Grid(p)
+        g.step(p.steps)
+        out.append((g.field(0), g.flux(0)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+# ------------------------------------------------------------------------------------------ boundary errors
+def test_validator_and_errors():
+    from paper_2505_23963_amd import FdtdbError, Grid
+    from paper_2505_23963_amd.fdtdb import E_INVALID, E_STATE, E_UNSTABLE, E_DIVERGED
+    base = dict(name="err", ndim=1, n=(100, 1, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(10, 0, 0), dtype="f64")
+    # Drude mirror with eps_inf = 1 at omega_p = 10 is unstable at Courant 0.5
+    p = Problem(**base)
+    p.materials.append(Drude(box((40, 50)), omega_p=10.0, gamma=0.01, eps_inf=1.0))
+    with pytest.raises(FdtdbError) as ei:
+        Grid(p)
+    assert ei.value.status == E_UNSTABLE
+    # dispersive material inside the CPML
+    p = Problem(**base)
+    p.materials.append(LorentzBath(box((5, 20)), omega0=1.0, gamma0=0.0, eps_inf=1.0, sigma=0.05))
+    with pytest.raises(FdtdbError) as ei:
+        Grid(p)
+    assert ei.value.status == E_INVALID
+    # overlapping boxes
+    p = Problem(**base)
+    p.materials += [Drude(box((40, 50)), omega_p=1.0, gamma=0.01, eps_inf=2.0),
+                    Drude(box((45, 55)), omega_p=1.0, gamma=0.01, eps_inf=2.0)]
+    with pytest.raises(FdtdbError) as ei:
+        Grid(p)
+    assert ei.value.status == E_INVALID
+    # Courant above the 3D limit
+    with pytest.raises(FdtdbError) as ei:
+        Grid(Problem(name="c", ndim=3, n=(4, 4, 4), courant=0.6))
+    assert ei.value.status == E_UNSTABLE
+    # materials after the first step
+    from paper_2505_23963_amd.fdtdb import Box, lib
+    import ctypes as C
+    g = Grid(Problem(**base))
+    g.step(1)
+    b = Box()
+    b.lo[:] = [30, 0, 0]
+    b.hi[:] = [40, 1, 1]
+    assert lib().fdtdb_set_eps_inf(g.h, C.byref(b), 2.0, None) == E_STATE
+    # watchdog: a NaN planted from the host is reported by synchronize
+    bad = np.zeros(100)
+    bad[50] = np.nan
+    g.set_field(2, bad)
+    g.step(2)
+    with pytest.raises(FdtdbError) as ei:
+        g.synchronize()
+    assert ei.value.status == E_DIVERGED
+
+
+@pytest.mark.parametrize("eps_factor,ok", [(1.03, True), (0.97, False)])
+def test_validator_drude_bound_matches_propagator(oracle_lib, eps_factor, ok):
+    """The library's Drude acceptance agrees with the oracle's brute-force propagator spectrum."""
+    from paper_2505_23963_amd import FdtdbError, Grid
+    from tests.test_oracle_pins import one_step_map, _periodic_1d
+    wp = 6.0
+    eps = 0.25 * (wp ** 2 + 4.0) / 4.0 * eps_factor
+    lam = np.abs(np.linalg.eigvals(one_step_map(oracle_lib, _periodic_1d(8, [Drude(box((0, 8)), omega_p=wp,
+                                                                                    gamma=0.0, eps_inf=eps)]))))
+    stable = lam.max() < 1 + 1e-6
+    assert stable == ok
+    p = Problem(name="v", ndim=1, n=(8, 1, 1), bc=(PERIODIC, PERIODIC, PERIODIC), dtype="f64")
+    p.materials.append(Drude(box((0, 8)), omega_p=wp, gamma=0.0, eps_inf=eps))
+    if ok:
+        Grid(p)
+    else:
+        with pytest.raises(FdtdbError):
+            Grid(p)
