@@ -6,7 +6,8 @@
 
 namespace fdtdb {
 
-constexpr int kMaxSources = 8;
+constexpr int kMaxSources = 4;
+constexpr int kMaxModes = 64;
 constexpr int kMaxEnergy = 4;
 constexpr int kBlock = 256;          // threads per block of the stencil kernels
 constexpr int kDftSlots = 32;        // steps staged before a DFT flush
@@ -36,6 +37,14 @@ struct SourceDev {
     int comp;
     int lo[3], hi[3];
     double omega_c, tau, t0, amplitude;
+    double coef;                     // dt / eps_inf at the source cells
+    const double *profile;           // box-sized, or null
+};
+
+// Source descriptor carried in kernel arguments (uniform, read through scalar loads).
+struct SourceArg {
+    int comp;
+    int lo[3], hi[3];
     double coef;                     // dt / eps_inf at the source cells
     const double *profile;           // box-sized, or null
 };
@@ -70,8 +79,8 @@ struct EArgs {
     const float *cw;                 // learned closure weights (FP32)
     // sources and clock
     const Clock *clock;
-    const SourceDev *src;
     int nsrc;
+    SourceArg src[kMaxSources];
     // energy monitors
     int nen;
     EnergyDev en[kMaxEnergy];
@@ -98,6 +107,13 @@ struct DftArgs {
     const void *H[2];
     double *stage;           // [slot][4][npts]
     int slot;
+};
+
+// Bath coefficients passed by value: head = cE, cP, cPm; per mode a_j, b_j + 1, c_j, sa_j, sb_j.
+template <int NG>
+struct BathCoef {
+    double head[3];
+    double md[4 * (NG > 0 ? NG : 1)][5];
 };
 
 // Coefficient table layout of a bath / Lorentz material (FP64):

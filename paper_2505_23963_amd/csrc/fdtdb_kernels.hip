@@ -23,34 +23,6 @@ __device__ __forceinline__ double ldd(const void *p, long long i) {
     return (double)static_cast<const T *>(p)[i];
 }
 
-// value at coordinate-1 / coordinate+1 along an axis, with the axis boundary rule
-template <typename T>
-__device__ __forceinline__ double at_minus(const void *f, long long q, int coord, long long stride, int n, int per) {
-    if (coord > 0) return ldd<T>(f, q - stride);
-    return per ? ldd<T>(f, q + (long long)(n - 1) * stride) : 0.0;
-}
-template <typename T>
-__device__ __forceinline__ double at_plus(const void *f, long long q, int coord, long long stride, int n, int per) {
-    if (coord < n - 1) return ldd<T>(f, q + stride);
-    return per ? ldd<T>(f, q - (long long)(n - 1) * stride) : 0.0;
-}
-
-template <int DIM>
-__device__ __forceinline__ void unflatten(int t, const int *lo, const int *ext, int ext12, int &i, int &j, int &k) {
-    if (DIM == 1) {
-        i = lo[0] + t; j = 0; k = 0;
-    } else if (DIM == 2) {
-        int r = t / ext[1];
-        i = lo[0] + r; j = lo[1] + (t - r * ext[1]); k = 0;
-    } else {
-        int r = t / ext[2];
-        k = lo[2] + (t - r * ext[2]);
-        int r2 = r / ext[1];
-        i = lo[0] + r2;
-        j = lo[1] + (r - r2 * ext[1]);
-    }
-}
-
 __device__ __forceinline__ double warp_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
@@ -69,15 +41,109 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
     }
 }
 
+
+// Neighbour at coordinate-1 / coordinate+1 along an axis with the axis boundary rule, without
+// branches: the load always reads a valid address (the cell itself when the neighbour lies
+// beyond a non-periodic edge) and the value is then selected, so loads stay in one batch.
+template <typename T>
+__device__ __forceinline__ double at_minus(const void *f, int q, int coord, int stride, int n, int per) {
+    const bool in = coord > 0;
+    const bool ok = in || per;
+    const int id = in ? q - stride : (per ? q + (n - 1) * stride : q);
+    const double v = (double)static_cast<const T *>(f)[id];
+    return ok ? v : 0.0;
+}
+template <typename T>
+__device__ __forceinline__ double at_plus(const void *f, int q, int coord, int stride, int n, int per) {
+    const bool in = coord < n - 1;
+    const bool ok = in || per;
+    const int id = in ? q + stride : (per ? q - (n - 1) * stride : q);
+    const double v = (double)static_cast<const T *>(f)[id];
+    return ok ? v : 0.0;
+}
+
+// soft-current term dt J(t_n) profile / eps of component c at cell (i, j, k)
+__device__ __forceinline__ double source_term(const EArgs &a, const double *amp, int c, int i, int j, int k) {
+    double s = 0.0;
+#pragma unroll
+    for (int n = 0; n < kMaxSources; ++n) {
+        if (n >= a.nsrc) break;
+        const SourceArg &S = a.src[n];
+        if (S.comp != c) continue;
+        if (i < S.lo[0] || i >= S.hi[0] || j < S.lo[1] || j >= S.hi[1] || k < S.lo[2] || k >= S.hi[2]) continue;
+        double prof = 1.0;
+        if (S.profile) {
+            const long long sl = ((long long)(i - S.lo[0]) * (S.hi[1] - S.lo[1]) + (j - S.lo[1])) * (S.hi[2] - S.lo[2]) + (k - S.lo[2]);
+            prof = S.profile[sl];
+        }
+        s += S.coef * amp[n] * prof;
+    }
+    return s;
+}
+
+// J(t_n) of every source slot (unused slots hold zero), requested together
+__device__ __forceinline__ void load_amps(const EArgs &a, double *amp) {
+#pragma unroll
+    for (int n = 0; n < kMaxSources; ++n) amp[n] = a.clock->amp[n];
+}
+
+// per-block energy partials of every monitor that samples this step
+__device__ __forceinline__ void energy_partials(const EArgs &a, bool live, int i, int j, int k, double ef, double ep,
+                                                double eb) {
+    for (int e = 0; e < a.nen; ++e) {
+        const EnergyDev &M = a.en[e];
+        if ((a.clock->step % M.every) != 0) continue;
+        const bool in = live && i >= M.lo[0] && i < M.hi[0] && j >= M.lo[1] && j < M.hi[1] && k >= M.lo[2] && k < M.hi[2];
+        double f0 = in ? ef : 0.0, f1 = in ? ep : 0.0, f2 = in ? eb : 0.0;
+        block_sum3(f0, f1, f2);
+        if (threadIdx.x == 0) {
+            double *out = M.partial + (a.block_base + blockIdx.x) * 3;
+            out[0] = f0; out[1] = f1; out[2] = f2;
+        }
+        __syncthreads();
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Remap so
+// that each XCD walks one contiguous run of the region in memory order: the y-1 / x-1 halo
+// rows a block reads were then written or read shortly before by the same XCD and sit in
+// its L2.  Bijective for any block count.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// 4-wide native vectors for non-temporal (streaming) loads and stores
+typedef float nv4f __attribute__((ext_vector_type(4)));
+typedef double nv4d __attribute__((ext_vector_type(4)));
+template <typename T>
+using nvec4_t = typename std::conditional<std::is_same<T, float>::value, nv4f, nv4d>::type;
+
+template <int DIM>
+__device__ __forceinline__ void unflatten(int t, const int *lo, const int *ext, int ext12, int &i, int &j, int &k) {
+    if (DIM == 1) {
+        i = lo[0] + t; j = 0; k = 0;
+    } else if (DIM == 2) {
+        int r = t / ext[1];
+        i = lo[0] + r; j = lo[1] + (t - r * ext[1]); k = 0;
+    } else {
+        int r = t / ext[2];
+        k = lo[2] + (t - r * ext[2]);
+        int r2 = r / ext[1];
+        i = lo[0] + r2;
+        j = lo[1] + (r - r2 * ext[1]);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
-// E / material update
+// E / material update, generic form: background (vacuum, dielectric, CPML), Drude, and the
+// Lorentz-Bath path for baths too large for the load-first kernel.
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, int KIND, int NG, bool PML, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     using V4 = vec4_t<T>;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const bool live = t < a.ext[0] * a.ext12;
-    const long long s0 = (long long)a.n[1] * a.n[2], s1 = a.n[2];
     double ef = 0.0, ep = 0.0, eb = 0.0;   // energy densities of this cell (when sampled)
     bool sample = false;
     if (ENERGY) {
@@ -86,14 +152,17 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     }
     int i = 0, j = 0, k = 0;
     if (live) {
+        double amp[kMaxSources];
+        load_amps(a, amp);
         unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
-        const long long q = i * s0 + j * s1 + k;
+        const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+        const int q = i * s0 + j * s1 + k;
         const int coord[3] = {i, j, k};
-        const long long stride[3] = {s0, s1, 1};
-        long long m = 0;
+        const int stride[3] = {s0, s1, 1};
+        int m = 0;
         double sig = a.sigma0;
         if (KIND != K_BACKGROUND) {
-            m = ((long long)(i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+            m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
             if (a.sigma) sig = ldd<T>(a.sigma, m);
         }
 #pragma unroll
@@ -108,33 +177,19 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
             if (PML) {
                 if (a.psi[c][0]) {
                     T *ps = static_cast<T *>(a.psi[c][0]);
-                    const long long r = t;
-                    const double psi = a.pml_b[a1][coord[a1]] * (double)ps[r] + a.pml_c[a1][coord[a1]] * t1;
-                    ps[r] = (T)psi;
+                    const double psi = a.pml_b[a1][coord[a1]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a1][coord[a1]] * t1;
+                    __builtin_nontemporal_store((T)psi, ps + t);
                     t1 += psi;
                 }
                 if (a.psi[c][1]) {
                     T *ps = static_cast<T *>(a.psi[c][1]);
-                    const long long r = t;
-                    const double psi = a.pml_b[a2][coord[a2]] * (double)ps[r] + a.pml_c[a2][coord[a2]] * t2;
-                    ps[r] = (T)psi;
+                    const double psi = a.pml_b[a2][coord[a2]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a2][coord[a2]] * t2;
+                    __builtin_nontemporal_store((T)psi, ps + t);
                     t2 += psi;
                 }
             }
             const double curl = t1 - t2;
-            // soft current sources on this component
-            double srcterm = 0.0;
-            for (int s = 0; s < a.nsrc; ++s) {
-                const SourceDev &S = a.src[s];
-                if (S.comp != c) continue;
-                if (i < S.lo[0] || i >= S.hi[0] || j < S.lo[1] || j >= S.hi[1] || k < S.lo[2] || k >= S.hi[2]) continue;
-                double prof = 1.0;
-                if (S.profile) {
-                    const long long sl = ((long long)(i - S.lo[0]) * (S.hi[1] - S.lo[1]) + (j - S.lo[1])) * (S.hi[2] - S.lo[2]) + (k - S.lo[2]);
-                    prof = S.profile[sl];
-                }
-                srcterm += S.coef * a.clock->amp[s] * prof;
-            }
+            const double srcterm = source_term(a, amp, c, i, j, k);
             T *Ec = static_cast<T *>(a.E[c]);
             const double Eo = (double)Ec[q];
             double En;
@@ -143,9 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 if (ENERGY && sample) ef += 0.5 / a.inv_eps * Eo * En;
             } else if (KIND == K_DRUDE) {
                 T *Vp = static_cast<T *>(a.Pcur[c]);
-                const double V = (double)Vp[m];
+                const double V = (double)__builtin_nontemporal_load(Vp + m);
                 En = Eo + a.inv_eps * (a.dt * curl - V) - srcterm;
-                Vp[m] = (T)(a.coef[0] * En + a.coef[1] * V);
+                __builtin_nontemporal_store((T)(a.coef[0] * En + a.coef[1] * V), Vp + m);
                 if (ENERGY && sample) {
                     ef += 0.5 / a.inv_eps * Eo * En;
                     const double v = V / a.dt;
@@ -193,14 +248,11 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
 #pragma unroll
                     for (int g = 0; g < NG; ++g) {
                         const double *md = cf + kCoefHead + 4 * g * kCoefMode;
-                        const double c0 = (double)yc[g].x, p0 = (double)yp[g].x;
-                        const double c1 = (double)yc[g].y, p1 = (double)yp[g].y;
-                        const double c2 = (double)yc[g].z, p2 = (double)yp[g].z;
-                        const double c3 = (double)yc[g].w, p3 = (double)yp[g].w;
-                        bsum += (c0 - p0) * (c0 - p0) / (a.dt * a.dt) + md[0 * kCoefMode + 5] * c0 * p0;
-                        bsum += (c1 - p1) * (c1 - p1) / (a.dt * a.dt) + md[1 * kCoefMode + 5] * c1 * p1;
-                        bsum += (c2 - p2) * (c2 - p2) / (a.dt * a.dt) + md[2 * kCoefMode + 5] * c2 * p2;
-                        bsum += (c3 - p3) * (c3 - p3) / (a.dt * a.dt) + md[3 * kCoefMode + 5] * c3 * p3;
+                        const double y0[4] = {(double)yc[g].x, (double)yc[g].y, (double)yc[g].z, (double)yc[g].w};
+                        const double y1[4] = {(double)yp[g].x, (double)yp[g].y, (double)yp[g].z, (double)yp[g].w};
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            bsum += (y0[u] - y1[u]) * (y0[u] - y1[u]) / (a.dt * a.dt) + md[u * kCoefMode + 5] * y0[u] * y1[u];
                     }
                     eb += 0.5 * rho * bsum;
                 }
@@ -216,36 +268,145 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 }
         }
     }
-    if (ENERGY && sample) {
-        // one partial per monitor per block; cells outside a monitor's box contribute zero
-        for (int e = 0; e < a.nen; ++e) {
-            const EnergyDev &M = a.en[e];
-            if ((a.clock->step % M.every) != 0) continue;
-            const bool in = live && i >= M.lo[0] && i < M.hi[0] && j >= M.lo[1] && j < M.hi[1] && k >= M.lo[2] && k < M.hi[2];
-            double f0 = in ? ef : 0.0, f1 = in ? ep : 0.0, f2 = in ? eb : 0.0;
-            block_sum3(f0, f1, f2);
-            if (threadIdx.x == 0) {
-                double *out = M.partial + (a.block_base + blockIdx.x) * 3;
-                out[0] = f0; out[1] = f1; out[2] = f2;
-            }
-            __syncthreads();
-        }
-    }
+    if (ENERGY && sample) energy_partials(a, live, i, j, k, ef, ep, eb);
 }
 
 // ---------------------------------------------------------------------------------------------
-// H update
+// Lorentz-Bath E update, load-first form.  Every load of the cell (E, the H values of the
+// curls, both polarization levels, both bath levels of every component) is issued before any
+// arithmetic or store, with neighbour reads branch-free, so a wave keeps its whole working set
+// in flight; the bath coefficients arrive by value in the kernel arguments (scalar loads).
+// E, P and the bath are then advanced in FP64 registers and written once.  Used when the bath
+// of all components fits the register budget (components x groups <= 16).
+// ---------------------------------------------------------------------------------------------
+template <int DIM, typename T, int NG, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const BathCoef<NG> cf) {
+    using V4 = nvec4_t<T>;
+    constexpr int NC = DIM == 3 ? 3 : 1;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int t = lb * kBlock + threadIdx.x;
+    const bool live = t < a.ext[0] * a.ext12;
+    double ef = 0.0, ep = 0.0, eb = 0.0;
+    bool sample = false;
+    if (ENERGY) {
+        const long long st = a.clock->step;
+        for (int e = 0; e < a.nen; ++e) sample |= (st % a.en[e].every) == 0;
+    }
+    int i = 0, j = 0, k = 0;
+    if (live) {
+        unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
+        const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+        const int q = i * s0 + j * s1 + k;
+        const int coord[3] = {i, j, k};
+        const int stride[3] = {s0, s1, 1};
+        const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+        const int mcells = (int)a.mcells;
+        // ---- phase 1: every load of the cell
+        double Eo[NC], Pc[NC], Pp[NC], t1[NC], t2[NC];
+        V4 yc[NC][NG], yp[NC][NG];
+        // per-cell sigma without a branch: with no sigma array the load reads the cell's own E
+        const bool has_sig = a.sigma != nullptr;
+        const T *sp = has_sig ? static_cast<const T *>(a.sigma) + m : static_cast<const T *>(a.E[DIM == 3 ? 0 : 2]) + q;
+        const T sig_raw = *sp;
+#pragma unroll
+        for (int ci = 0; ci < NC; ++ci) {
+            const int c = DIM == 3 ? ci : 2;
+            const int a1 = curl_a1(c), a2 = curl_a2(c);
+            t1[ci] = 0.0;
+            t2[ci] = 0.0;
+            if (axis_live(DIM, a1) && h_active(DIM, a2))
+                t1[ci] = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+            if (axis_live(DIM, a2) && h_active(DIM, a1))
+                t2[ci] = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+            Eo[ci] = (double)static_cast<const T *>(a.E[c])[q];
+            // polarization and bath levels are read once and written once per step: stream them
+            Pc[ci] = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pcur[c]) + m);
+            Pp[ci] = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pnew[c]) + m);
+            const V4 *Yc = static_cast<const V4 *>(a.Ycur[c]);
+            const V4 *Yp = static_cast<const V4 *>(a.Ynew[c]);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                yc[ci][g] = __builtin_nontemporal_load(Yc + g * mcells + m);
+                yp[ci][g] = __builtin_nontemporal_load(Yp + g * mcells + m);
+            }
+        }
+        double amp[kMaxSources];
+        load_amps(a, amp);
+        const double sig = has_sig ? (double)sig_raw : a.sigma0;
+        // ---- phase 2: arithmetic and stores
+#pragma unroll
+        for (int ci = 0; ci < NC; ++ci) {
+            const int c = DIM == 3 ? ci : 2;
+            const double srcterm = source_term(a, amp, c, i, j, k);
+            const double En = Eo[ci] + a.inv_eps * (a.dt * (t1[ci] - t2[ci]) - (Pc[ci] - Pp[ci])) - srcterm;
+            double S = 0.0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const double yv0[4] = {(double)yc[ci][g].x, (double)yc[ci][g].y, (double)yc[ci][g].z, (double)yc[ci][g].w};
+                const double yv1[4] = {(double)yp[ci][g].x, (double)yp[ci][g].y, (double)yp[ci][g].z, (double)yp[ci][g].w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) S += cf.md[4 * g + u][3] * yv0[u] + cf.md[4 * g + u][4] * yv1[u];
+            }
+            const double Pnew = cf.head[0] * sig * En - cf.head[1] * Pc[ci] - cf.head[2] * Pp[ci] - S;
+            const double dP = Pnew - Pp[ci];
+            static_cast<T *>(a.E[c])[q] = (T)En;
+            __builtin_nontemporal_store((T)Pnew, static_cast<T *>(a.Pnew[c]) + m);
+            V4 *Yn = static_cast<V4 *>(a.Ynew[c]);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const double yv0[4] = {(double)yc[ci][g].x, (double)yc[ci][g].y, (double)yc[ci][g].z, (double)yc[ci][g].w};
+                const double yv1[4] = {(double)yp[ci][g].x, (double)yp[ci][g].y, (double)yp[ci][g].z, (double)yp[ci][g].w};
+                double r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r[u] = cf.md[4 * g + u][0] * yv0[u] + cf.md[4 * g + u][1] * yv1[u] + cf.md[4 * g + u][2] * dP;
+                V4 o;
+                o.x = (T)r[0]; o.y = (T)r[1]; o.z = (T)r[2]; o.w = (T)r[3];
+                __builtin_nontemporal_store(o, Yn + g * mcells + m);
+            }
+            if (ENERGY && sample) {
+                ef += 0.5 / a.inv_eps * Eo[ci] * En;
+                const double *tab = a.coef;   // energy constants from the global table
+                const double rho = tab[3] / sig;
+                const double v = (Pc[ci] - Pp[ci]) / a.dt;
+                ep += 0.5 * rho * (v * v + tab[4] * Pc[ci] * Pp[ci]);
+                double bsum = 0.0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const double y0[4] = {(double)yc[ci][g].x, (double)yc[ci][g].y, (double)yc[ci][g].z, (double)yc[ci][g].w};
+                    const double y1[4] = {(double)yp[ci][g].x, (double)yp[ci][g].y, (double)yp[ci][g].z, (double)yp[ci][g].w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        bsum += (y0[u] - y1[u]) * (y0[u] - y1[u]) / (a.dt * a.dt) +
+                                tab[kCoefHead + (4 * g + u) * kCoefMode + 5] * y0[u] * y1[u];
+                }
+                eb += 0.5 * rho * bsum;
+            }
+        }
+        if (ENERGY && sample) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (h_active(DIM, c)) {
+                    const double h = ldd<T>(a.H[c], q);
+                    ef += 0.5 * h * h;
+                }
+        }
+    }
+    if (ENERGY && sample) energy_partials(a, live, i, j, k, ef, ep, eb);
+}
+
+// ---------------------------------------------------------------------------------------------
+// H update, generic form
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, bool PML>
 __global__ __launch_bounds__(kBlock) void k_update_h(const HArgs a) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (t >= a.ext[0] * a.ext12) return;
     int i, j, k;
     unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
-    const long long s0 = (long long)a.n[1] * a.n[2], s1 = a.n[2];
-    const long long q = i * s0 + j * s1 + k;
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
     const int coord[3] = {i, j, k};
-    const long long stride[3] = {s0, s1, 1};
+    const int stride[3] = {s0, s1, 1};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (!h_active(DIM, c)) continue;
@@ -258,20 +419,87 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const HArgs a) {
         if (PML) {
             if (a.psi[c][0]) {
                 T *ps = static_cast<T *>(a.psi[c][0]);
-                const double psi = a.pml_b[a1][coord[a1]] * (double)ps[t] + a.pml_c[a1][coord[a1]] * t1;
-                ps[t] = (T)psi;
+                const double psi = a.pml_b[a1][coord[a1]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a1][coord[a1]] * t1;
+                __builtin_nontemporal_store((T)psi, ps + t);
                 t1 += psi;
             }
             if (a.psi[c][1]) {
                 T *ps = static_cast<T *>(a.psi[c][1]);
-                const double psi = a.pml_b[a2][coord[a2]] * (double)ps[t] + a.pml_c[a2][coord[a2]] * t2;
-                ps[t] = (T)psi;
+                const double psi = a.pml_b[a2][coord[a2]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a2][coord[a2]] * t2;
+                __builtin_nontemporal_store((T)psi, ps + t);
                 t2 += psi;
             }
         }
         T *Hc = static_cast<T *>(a.H[c]);
         Hc[q] = (T)((double)Hc[q] - a.dt * (t1 - t2));
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// 3D H update over a z-aligned region without CPML, four z-consecutive cells per thread:
+// 16-byte loads of the own E and H rows and of the y+1 / x+1 neighbour rows, one scalar load
+// for the z+1 neighbour of the last cell.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ double lane4(const vec4_t<T> &v, int e) {
+    return e == 0 ? (double)v.x : e == 1 ? (double)v.y : e == 2 ? (double)v.z : (double)v.w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
+    using V = vec4_t<T>;
+    const int ext2q = a.ext[2] >> 2;
+    const int total = a.ext[0] * a.ext[1] * ext2q;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (t >= total) return;
+    const int r = t / ext2q;
+    const int k = a.lo[2] + 4 * (t - r * ext2q);
+    const int r2 = r / a.ext[1];
+    const int i = a.lo[0] + r2, j = a.lo[1] + (r - r2 * a.ext[1]);
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const T *Ex = static_cast<const T *>(a.E[0]);
+    const T *Ey = static_cast<const T *>(a.E[1]);
+    const T *Ez = static_cast<const T *>(a.E[2]);
+    // neighbour rows with the axis boundary rule; an invalid neighbour reads the own row, then is zeroed
+    const bool oky = j < a.n[1] - 1 || a.per[1], okx = i < a.n[0] - 1 || a.per[0], okz = k + 4 < a.n[2] || a.per[2];
+    const int qy = j < a.n[1] - 1 ? q + s1 : (a.per[1] ? q - (a.n[1] - 1) * s1 : q);
+    const int qx = i < a.n[0] - 1 ? q + s0 : (a.per[0] ? q - (a.n[0] - 1) * s0 : q);
+    const int qz = k + 4 < a.n[2] ? q + 4 : (a.per[2] ? q + 4 - a.n[2] : q);
+    const V ex = *reinterpret_cast<const V *>(Ex + q);
+    const V ey = *reinterpret_cast<const V *>(Ey + q);
+    const V ez = *reinterpret_cast<const V *>(Ez + q);
+    const V ez_y = *reinterpret_cast<const V *>(Ez + qy);
+    const V ex_y = *reinterpret_cast<const V *>(Ex + qy);
+    const V ey_x = *reinterpret_cast<const V *>(Ey + qx);
+    const V ez_x = *reinterpret_cast<const V *>(Ez + qx);
+    const double ex_z = okz ? (double)Ex[qz] : 0.0;
+    const double ey_z = okz ? (double)Ey[qz] : 0.0;
+    V *Hx = reinterpret_cast<V *>(static_cast<T *>(a.H[0]) + q);
+    V *Hy = reinterpret_cast<V *>(static_cast<T *>(a.H[1]) + q);
+    V *Hz = reinterpret_cast<V *>(static_cast<T *>(a.H[2]) + q);
+    const V hx = *Hx, hy = *Hy, hz = *Hz;
+    const double dt = a.dt;
+    double ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double exe = lane4<T>(ex, e), eye = lane4<T>(ey, e), eze = lane4<T>(ez, e);
+        const double exn = e < 3 ? lane4<T>(ex, e + 1) : ex_z;
+        const double eyn = e < 3 ? lane4<T>(ey, e + 1) : ey_z;
+        const double ezy = oky ? lane4<T>(ez_y, e) : 0.0, exy = oky ? lane4<T>(ex_y, e) : 0.0;
+        const double eyx = okx ? lane4<T>(ey_x, e) : 0.0, ezx = okx ? lane4<T>(ez_x, e) : 0.0;
+        // Hx -= dt (d_y Ez - d_z Ey); Hy -= dt (d_z Ex - d_x Ez); Hz -= dt (d_x Ey - d_y Ex)
+        ox[e] = lane4<T>(hx, e) - dt * ((ezy - eze) - (eyn - eye));
+        oy[e] = lane4<T>(hy, e) - dt * ((exn - exe) - (ezx - eze));
+        oz[e] = lane4<T>(hz, e) - dt * ((eyx - eye) - (exy - exe));
+    }
+    V wx, wy, wz;
+    wx.x = (T)ox[0]; wx.y = (T)ox[1]; wx.z = (T)ox[2]; wx.w = (T)ox[3];
+    wy.x = (T)oy[0]; wy.y = (T)oy[1]; wy.z = (T)oy[2]; wy.w = (T)oy[3];
+    wz.x = (T)oz[0]; wz.y = (T)oz[1]; wz.z = (T)oz[2]; wz.w = (T)oz[3];
+    *Hx = wx;
+    *Hy = wy;
+    *Hz = wz;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -415,9 +643,21 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *f, long long n, i
 static inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <int DIM, typename T, int KIND, int NG, bool PML>
-static hipError_t launch_e_pml(const EArgs &a, bool energy, hipStream_t s) {
+static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool energy, hipStream_t s) {
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
+    constexpr int NC = DIM == 3 ? 3 : 1;
+    if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16) {
+        BathCoef<NG> cf;
+        for (int h = 0; h < 3; ++h) cf.head[h] = coef_host[h];
+        for (int j = 0; j < 4 * NG; ++j)
+            for (int u = 0; u < 5; ++u) cf.md[j][u] = coef_host[kCoefHead + j * kCoefMode + u];
+        if (energy)
+            hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
+        else
+            hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
+        return hipGetLastError();
+    }
     if (energy)
         hipLaunchKernelGGL((k_update_e<DIM, T, KIND, NG, PML, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
     else
@@ -426,44 +666,48 @@ static hipError_t launch_e_pml(const EArgs &a, bool energy, hipStream_t s) {
 }
 
 template <int DIM, typename T>
-static hipError_t launch_e_dim(const EArgs &a, int kind, int ng, bool pml, bool energy, hipStream_t s) {
+static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int ng, bool pml, bool energy, hipStream_t s) {
     if (kind == K_BACKGROUND)
-        return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, energy, s)
-                   : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, energy, s);
-    if (kind == K_DRUDE) return launch_e_pml<DIM, T, K_DRUDE, 0, false>(a, energy, s);
+        return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, ch, energy, s)
+                   : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, ch, energy, s);
+    if (kind == K_DRUDE) return launch_e_pml<DIM, T, K_DRUDE, 0, false>(a, ch, energy, s);
     if (kind == K_BATH) {
         switch (ng) {
-            case 0: return launch_e_pml<DIM, T, K_BATH, 0, false>(a, energy, s);
-            case 1: return launch_e_pml<DIM, T, K_BATH, 1, false>(a, energy, s);
-            case 2: return launch_e_pml<DIM, T, K_BATH, 2, false>(a, energy, s);
-            case 3: return launch_e_pml<DIM, T, K_BATH, 3, false>(a, energy, s);
-            case 4: return launch_e_pml<DIM, T, K_BATH, 4, false>(a, energy, s);
-            case 6: return launch_e_pml<DIM, T, K_BATH, 6, false>(a, energy, s);
-            case 8: return launch_e_pml<DIM, T, K_BATH, 8, false>(a, energy, s);
-            case 12: return launch_e_pml<DIM, T, K_BATH, 12, false>(a, energy, s);
-            case 16: return launch_e_pml<DIM, T, K_BATH, 16, false>(a, energy, s);
+            case 0: return launch_e_pml<DIM, T, K_BATH, 0, false>(a, ch, energy, s);
+            case 1: return launch_e_pml<DIM, T, K_BATH, 1, false>(a, ch, energy, s);
+            case 2: return launch_e_pml<DIM, T, K_BATH, 2, false>(a, ch, energy, s);
+            case 3: return launch_e_pml<DIM, T, K_BATH, 3, false>(a, ch, energy, s);
+            case 4: return launch_e_pml<DIM, T, K_BATH, 4, false>(a, ch, energy, s);
+            case 6: return launch_e_pml<DIM, T, K_BATH, 6, false>(a, ch, energy, s);
+            case 8: return launch_e_pml<DIM, T, K_BATH, 8, false>(a, ch, energy, s);
+            case 12: return launch_e_pml<DIM, T, K_BATH, 12, false>(a, ch, energy, s);
+            case 16: return launch_e_pml<DIM, T, K_BATH, 16, false>(a, ch, energy, s);
             default: return hipErrorInvalidValue;
         }
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_update_e(int dim, bool f64, const EArgs &a, int kind, int ng, bool pml, bool energy,
-                           hipStream_t s) {
+hipError_t launch_update_e(int dim, bool f64, const EArgs &a, const double *coef_host, int kind, int ng, bool pml,
+                           bool energy, hipStream_t s) {
     if (f64) {
-        if (dim == 1) return launch_e_dim<1, double>(a, kind, ng, pml, energy, s);
-        if (dim == 2) return launch_e_dim<2, double>(a, kind, ng, pml, energy, s);
-        return launch_e_dim<3, double>(a, kind, ng, pml, energy, s);
+        if (dim == 1) return launch_e_dim<1, double>(a, coef_host, kind, ng, pml, energy, s);
+        if (dim == 2) return launch_e_dim<2, double>(a, coef_host, kind, ng, pml, energy, s);
+        return launch_e_dim<3, double>(a, coef_host, kind, ng, pml, energy, s);
     }
-    if (dim == 1) return launch_e_dim<1, float>(a, kind, ng, pml, energy, s);
-    if (dim == 2) return launch_e_dim<2, float>(a, kind, ng, pml, energy, s);
-    return launch_e_dim<3, float>(a, kind, ng, pml, energy, s);
+    if (dim == 1) return launch_e_dim<1, float>(a, coef_host, kind, ng, pml, energy, s);
+    if (dim == 2) return launch_e_dim<2, float>(a, coef_host, kind, ng, pml, energy, s);
+    return launch_e_dim<3, float>(a, coef_host, kind, ng, pml, energy, s);
 }
 
 template <int DIM, typename T>
 static hipError_t launch_h_dim(const HArgs &a, bool pml, hipStream_t s) {
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
+    if (DIM == 3 && !pml && a.lo[2] % 4 == 0 && a.ext[2] % 4 == 0 && a.n[2] % 4 == 0) {
+        hipLaunchKernelGGL(k_update_h3_v4<T>, dim3(nblocks(n / 4)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     if (pml)
         hipLaunchKernelGGL((k_update_h<DIM, T, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
     else

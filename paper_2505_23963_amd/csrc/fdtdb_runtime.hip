@@ -15,7 +15,8 @@
 #include "fdtdb_internal.h"
 
 namespace fdtdb {
-hipError_t launch_update_e(int dim, bool f64, const EArgs &a, int kind, int ng, bool pml, bool energy, hipStream_t s);
+hipError_t launch_update_e(int dim, bool f64, const EArgs &a, const double *coef_host, int kind, int ng, bool pml,
+                           bool energy, hipStream_t s);
 hipError_t launch_update_h(int dim, bool f64, const HArgs &a, bool pml, hipStream_t s);
 hipError_t launch_tick(Clock *clk, const SourceDev *src, int nsrc, double dt, hipStream_t s);
 hipError_t launch_energy_reduce(const Clock *clk, const double *partial, long long nslots, int every, double *out,
@@ -134,7 +135,8 @@ struct fdtdb_grid_s {
     std::vector<Source> srcs;
     std::vector<Dft> dfts;
     std::vector<Energy> ens;
-    std::vector<Region> regions;
+    std::vector<Region> regions;    // E / material update regions
+    std::vector<Region> hregions;   // H update regions (CPML partition only)
     double *pml_b[3] = {}, *pml_c[3] = {}, *pml_bh[3] = {}, *pml_ch[3] = {};
     Clock *clock = nullptr;
     SourceDev *src_dev = nullptr;
@@ -231,7 +233,10 @@ double pml_sigma(const fdtdb_grid_s *g, int a, double pos) {
 }
 
 // ---------------------------------------------------------------------------- region partition
-fdtdb_status build_regions(fdtdb_grid_s *g) {
+// Split the grid into boxes of uniform update: cut at every material and CPML edge, then grow
+// boxes greedily (z, then y, then x) over cuts of equal attributes.  E regions carry
+// (material, CPML mask); H regions only the CPML mask (the H update is material-free).
+void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) {
     std::vector<int> br[3];
     for (int a = 0; a < 3; a++) {
         br[a].push_back(0);
@@ -240,10 +245,11 @@ fdtdb_status build_regions(fdtdb_grid_s *g) {
             br[a].push_back(g->pml[a]);
             br[a].push_back(g->n[a] - g->pml[a]);
         }
-        for (auto &m : g->mats) {
-            br[a].push_back((int)m.lo[a]);
-            br[a].push_back((int)m.hi[a]);
-        }
+        if (with_mats)
+            for (auto &m : g->mats) {
+                br[a].push_back((int)m.lo[a]);
+                br[a].push_back((int)m.hi[a]);
+            }
         std::sort(br[a].begin(), br[a].end());
         br[a].erase(std::unique(br[a].begin(), br[a].end()), br[a].end());
     }
@@ -257,7 +263,7 @@ fdtdb_status build_regions(fdtdb_grid_s *g) {
             for (int z = 0; z < nc; z++) {
                 const int64_t lo[3] = {br[0][x], br[1][y], br[2][z]};
                 int mat = -1;
-                for (size_t mi = 0; mi < g->mats.size(); mi++) {
+                for (size_t mi = 0; with_mats && mi < g->mats.size(); mi++) {
                     const Material &m = g->mats[mi];
                     if (lo[0] >= m.lo[0] && lo[0] < m.hi[0] && lo[1] >= m.lo[1] && lo[1] < m.hi[1] && lo[2] >= m.lo[2] &&
                         lo[2] < m.hi[2])
@@ -309,21 +315,27 @@ fdtdb_status build_regions(fdtdb_grid_s *g) {
                 r.mat = rev[id].first;
                 r.pml_mask = rev[id].second;
                 r.eps = r.mat >= 0 ? g->mats[r.mat].eps : 1.0;
-                g->regions.push_back(r);
+                out.push_back(r);
             }
+}
+
+fdtdb_status build_regions(fdtdb_grid_s *g) {
+    partition(g, true, g->regions);
+    partition(g, false, g->hregions);
     // CPML psi storage per region, per component and curl term whose axis is absorbing
-    for (auto &r : g->regions) {
-        if (!r.pml_mask) continue;
-        const long long nc_ = r.cells();
-        for (int c = 0; c < 3; c++) {
-            const int ax[2] = {curl_a1(c), curl_a2(c)};
-            for (int t = 0; t < 2; t++) {
-                if (!(r.pml_mask & (1 << ax[t]))) continue;
-                if (e_active(g->ndim, c)) TRY(g->alloc(&r.psiE[c][t], words(nc_, g->f64)));
-                if (h_active(g->ndim, c)) TRY(g->alloc(&r.psiH[c][t], words(nc_, g->f64)));
+    for (int h = 0; h < 2; h++)
+        for (auto &r : h ? g->hregions : g->regions) {
+            if (!r.pml_mask) continue;
+            const long long nc_ = r.cells();
+            for (int c = 0; c < 3; c++) {
+                const int ax[2] = {curl_a1(c), curl_a2(c)};
+                for (int t = 0; t < 2; t++) {
+                    if (!(r.pml_mask & (1 << ax[t]))) continue;
+                    if (!h && e_active(g->ndim, c)) TRY(g->alloc(&r.psiE[c][t], words(nc_, g->f64)));
+                    if (h && h_active(g->ndim, c)) TRY(g->alloc(&r.psiH[c][t], words(nc_, g->f64)));
+                }
             }
         }
-    }
     return FDTDB_OK;
 }
 
@@ -411,17 +423,18 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         e.nslots = base;
         TRY(g->alloc((void **)&e.partial, 24 * (size_t)base));
     }
-    g->launches_per_step = 1 + 2 * (int)g->regions.size() + (int)g->ens.size() + (int)g->dfts.size();
-    for (size_t ri = 0; ri < g->regions.size(); ri++) {
-        const Region &r = g->regions[ri];
-        double be, bh;
-        region_bytes(g, r, &be, &bh);
-        for (int ph = 0; ph < 2; ph++) {
+    g->launches_per_step = 1 + (int)g->regions.size() + (int)g->hregions.size() + (int)g->ens.size() + (int)g->dfts.size();
+    for (int ph = 0; ph < 2; ph++) {
+        const std::vector<Region> &rs = ph ? g->hregions : g->regions;
+        for (size_t ri = 0; ri < rs.size(); ri++) {
+            const Region &r = rs[ri];
+            double be, bh;
+            region_bytes(g, r, &be, &bh);
             fdtdb_kernel_record k{};
             k.region = (int)ri;
             k.phase = ph;
             k.kind = ph == 0 && r.mat >= 0 ? g->mats[r.mat].kind : K_BACKGROUND;
-            k.n_bath = r.mat >= 0 ? g->mats[r.mat].nb : 0;
+            k.n_bath = ph == 0 && r.mat >= 0 ? g->mats[r.mat].nb : 0;
             k.pml = r.pml_mask != 0;
             k.cells = r.cells();
             k.bytes = (ph == 0 ? be : bh) * (double)r.cells();
@@ -529,8 +542,15 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             a.coef = m.coef_dev;
         }
         a.clock = g->clock;
-        a.src = g->src_dev;
         a.nsrc = (int)g->srcs.size();
+        for (int s = 0; s < a.nsrc; s++) {
+            const Source &S = g->srcs[s];
+            SourceArg &d = a.src[s];
+            d.comp = S.comp;
+            for (int ax = 0; ax < 3; ax++) { d.lo[ax] = (int)S.lo[ax]; d.hi[ax] = (int)S.hi[ax]; }
+            d.coef = g->dt / S.eps;
+            d.profile = S.profile_dev;
+        }
         a.nen = 0;
         if (r.energy) {
             for (auto &e : g->ens) {
@@ -541,7 +561,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             }
         }
         a.block_base = r.block_base;
-        const int rec = 2 * (int)(&r - &g->regions[0]);
+        const int rec = (int)(&r - &g->regions[0]);
         Pending pe{rec, nullptr, nullptr};
         if (g->profiling) {
             pe.a = take_event(g);
@@ -549,7 +569,8 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
             HIP_TRY(hipEventRecord(pe.a, g->stream));
         }
-        HIP_TRY(launch_update_e(g->ndim, g->f64, a, kind, ng, r.pml_mask != 0, r.energy, g->stream));
+        const double *ch = r.mat >= 0 && !g->mats[r.mat].coef.empty() ? g->mats[r.mat].coef.data() : nullptr;
+        HIP_TRY(launch_update_e(g->ndim, g->f64, a, ch, kind, ng, r.pml_mask != 0, r.energy, g->stream));
         if (g->profiling) {
             HIP_TRY(hipEventRecord(pe.b, g->stream));
             g->pending.push_back(pe);
@@ -557,7 +578,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     }
     for (auto &e : g->ens)
         HIP_TRY(launch_energy_reduce(g->clock, e.partial, e.nslots, e.every, e.out, e.capacity, g->stream));
-    for (auto &r : g->regions) {
+    for (auto &r : g->hregions) {
         HArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
         fill_fields(g, a.n, a.per);
@@ -567,7 +588,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         for (int c = 0; c < 3; c++)
             for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiH[c][t];
         for (int ax = 0; ax < 3; ax++) { a.pml_b[ax] = g->pml_bh[ax]; a.pml_c[ax] = g->pml_ch[ax]; }
-        const int rec = 2 * (int)(&r - &g->regions[0]) + 1;
+        const int rec = (int)g->regions.size() + (int)(&r - &g->hregions[0]);
         Pending pe{rec, nullptr, nullptr};
         if (g->profiling) {
             pe.a = take_event(g);
@@ -1098,11 +1119,15 @@ fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out) {
     fdtdb_stats s{};
     s.cells = g->ncell;
     double be = 0.0, bh = 0.0;
+    for (auto &r : g->hregions) {
+        double e, h;
+        region_bytes(g, r, &e, &h);
+        bh += h * (double)r.cells();
+    }
     for (auto &r : g->regions) {
         double e, h;
         region_bytes(g, r, &e, &h);
         be += e * (double)r.cells();
-        bh += h * (double)r.cells();
         if (r.mat >= 0 && g->mats[r.mat].kind != K_BACKGROUND) {
             s.dispersive_cells += r.cells();
             if (g->mats[r.mat].nb) s.bath_cells += r.cells();
