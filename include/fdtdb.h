@@ -236,6 +236,52 @@ typedef struct {
  * capacity records (two per region) to out; *count receives the number. */
 fdtdb_status fdtdb_kernel_records(fdtdb_grid g, fdtdb_kernel_record *out, int capacity, int *count);
 
+/* ------------------------------------------------------------------------------ batched cavities */
+/* Many independent 1D cavities (x axis, Ez / Hy, the grid conventions above)
+ * of uneven length advanced together.  Each workgroup keeps one segment of one
+ * cavity, with a halo of (steps per launch + 1) cells on each side, entirely in
+ * registers for several steps per launch (no HBM traffic between those steps),
+ * then writes it back; launches are replayed from a captured HIP graph.  The
+ * arithmetic is that of the grid path (FP64 registers, FP32 or FP64 storage).
+ * Limits: per cavity one Drude medium, one Lorentz-Bath medium with at most 32
+ * bath modes, one source cell, one DFT node (frequencies shared by all
+ * cavities), one energy box.  CPML of pml_cells cells at both ends of every
+ * cavity (0: closed ends).  FP64 storage uses 256-thread workgroups. */
+typedef struct fdtdb_batch_s *fdtdb_batch;
+
+/* lengths: ncav cell counts (copied).  Same error model as fdtdb_create_grid. */
+fdtdb_status fdtdb_batch_create(int ncav, const int64_t *lengths, fdtdb_dtype dtype, double courant, int pml_cells,
+                                double pml_R0, void *hip_stream, fdtdb_batch *out);
+fdtdb_status fdtdb_batch_destroy(fdtdb_batch b);
+/* Materials on cells [lo, hi) of cavity cav; same stability checks as the grid calls (ndim = 1). */
+fdtdb_status fdtdb_batch_set_drude(fdtdb_batch b, int cav, int64_t lo, int64_t hi, double omega_p, double gamma,
+                                   double eps_inf);
+fdtdb_status fdtdb_batch_set_lorentz_bath(fdtdb_batch b, int cav, int64_t lo, int64_t hi, double omega0,
+                                          double gamma0, double eps_inf, double sigma, int n_bath,
+                                          const double *omega_j, const double *gamma_j, const double *k_j);
+/* Soft current on Ez at cell x (the pulse of fdtdb_add_source). */
+fdtdb_status fdtdb_batch_add_source(fdtdb_batch b, int cav, int64_t x, double omega_c, double width, double amplitude);
+/* DFT flux node at cell x (1 <= x < L), the 1D case of fdtdb_add_dft_flux. */
+fdtdb_status fdtdb_batch_add_dft_flux(fdtdb_batch b, int cav, int64_t x, int nfreq, const double *omega);
+/* Exact discrete energy over cells [lo, hi) every `every` steps (fdtdb_add_energy_monitor). */
+fdtdb_status fdtdb_batch_add_energy_monitor(fdtdb_batch b, int cav, int64_t lo, int64_t hi, int every);
+/* Tile shape: steps per launch and threads per workgroup (256, 512 or 1024 for FP32; 256 for
+ * FP64).  steps_per_launch == 0 runs the autotuner, which times the candidate shapes on scratch
+ * copies of the state.  Only before the first step (E_STATE afterwards); the first
+ * fdtdb_batch_step autotunes if no shape was set. */
+fdtdb_status fdtdb_batch_set_tiling(fdtdb_batch b, int steps_per_launch, int threads_per_block);
+fdtdb_status fdtdb_batch_get_tiling(fdtdb_batch b, int *steps_per_launch, int *threads_per_block);
+fdtdb_status fdtdb_batch_step(fdtdb_batch b, int64_t nsteps);
+fdtdb_status fdtdb_batch_synchronize(fdtdb_batch b);
+fdtdb_status fdtdb_batch_steps_done(fdtdb_batch b, int64_t *steps);
+/* Read-outs (synchronize first): component 2 (Ez) or 4 (Hy), L doubles; flux nfreq doubles;
+ * energy capacity x 3 doubles [field, pol, bath]. */
+fdtdb_status fdtdb_batch_get_field(fdtdb_batch b, int cav, int component, double *out);
+fdtdb_status fdtdb_batch_dft_flux(fdtdb_batch b, int cav, double *flux);
+fdtdb_status fdtdb_batch_energy(fdtdb_batch b, int cav, double *out, int64_t capacity, int64_t *n_samples);
+/* Last error message of the batch calls on this thread. */
+const char *fdtdb_batch_last_error(void);
+
 /* Last error message on this thread ("" if none). */
 const char *fdtdb_last_error(void);
 

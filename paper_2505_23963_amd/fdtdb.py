@@ -78,6 +78,24 @@ SIGNATURES = [
     ("fdtdb_get_stats", C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     ("fdtdb_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
     ("fdtdb_kernel_records", C.c_int, [C.c_void_p, C.POINTER(KernelRecord), C.c_int, C.POINTER(C.c_int)]),
+    ("fdtdb_batch_create", C.c_int, [C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_double, C.c_int, C.c_double,
+                                     C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("fdtdb_batch_destroy", C.c_int, [C.c_void_p]),
+    ("fdtdb_batch_set_drude", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double]),
+    ("fdtdb_batch_set_lorentz_bath", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                               C.c_double, C.c_double, C.c_int, _dp, _dp, _dp]),
+    ("fdtdb_batch_add_source", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_double]),
+    ("fdtdb_batch_add_dft_flux", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, _dp]),
+    ("fdtdb_batch_add_energy_monitor", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int]),
+    ("fdtdb_batch_set_tiling", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("fdtdb_batch_get_tiling", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("fdtdb_batch_step", C.c_int, [C.c_void_p, C.c_int64]),
+    ("fdtdb_batch_synchronize", C.c_int, [C.c_void_p]),
+    ("fdtdb_batch_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("fdtdb_batch_get_field", C.c_int, [C.c_void_p, C.c_int, C.c_int, _dp]),
+    ("fdtdb_batch_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp]),
+    ("fdtdb_batch_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
+    ("fdtdb_batch_last_error", C.c_char_p, []),
     ("fdtdb_last_error", C.c_char_p, []),
     ("fdtdb_version", C.c_char_p, []),
 ]
@@ -263,3 +281,99 @@ class Grid:
         s = Stats()
         _check(lib().fdtdb_get_stats(self.h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def _bcheck(st: int):
+    if st != OK:
+        raise FdtdbError(st, lib().fdtdb_batch_last_error().decode())
+
+
+class Batch:
+    """Many independent 1D cavities advanced together (fdtdb_batch_* entry points).
+
+    Built from a list of 1D Problem descriptions that share dtype, courant and
+    CPML thickness; each may hold one Drude medium (possibly several boxes with
+    equal parameters), one Lorentz-Bath box, one source cell, one DFT node and one
+    energy box.
+    """
+
+    def __init__(self, problems, stream: Optional[int] = None, tiling=None, dtype: Optional[str] = None):
+        L = lib()
+        self.ps = list(problems)
+        p0 = self.ps[0]
+        n = len(self.ps)
+        lens = (C.c_int64 * n)(*[int(p.n[0]) for p in self.ps])
+        dt = dtype or p0.dtype
+        h = C.c_void_p()
+        pml = int(p0.pml_cells[0]) if p0.bc[0] == BC_PML else 0
+        _bcheck(L.fdtdb_batch_create(n, lens, F64 if dt == "f64" else F32, p0.courant, pml, p0.pml_R0, stream,
+                                     C.byref(h)))
+        self.h = h
+        for c, p in enumerate(self.ps):
+            for m in p.materials:
+                kind = type(m).__name__
+                lo, hi = int(m.box[0][0]), int(m.box[1][0])
+                if kind == "Drude":
+                    _bcheck(L.fdtdb_batch_set_drude(self.h, c, lo, hi, m.omega_p, m.gamma, m.eps_inf))
+                elif kind == "LorentzBath":
+                    if m.n_bath and m.form is not None:
+                        wj, gj, kj = bath_params(m.form, m.omega0, m.gamma0, m.n_bath, m.width, m.bath_gamma,
+                                                 m.dephasing)
+                    else:
+                        wj, gj, kj = _arr(m.omega_j), _arr(m.gamma_j), _arr(m.k_j)
+                    if m.sigma_cells is not None:
+                        raise ValueError("batched cavities take a uniform sigma")
+                    _bcheck(L.fdtdb_batch_set_lorentz_bath(self.h, c, lo, hi, m.omega0, m.gamma0, m.eps_inf, m.sigma,
+                                                           m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj)))
+                else:
+                    raise TypeError(kind)
+            for s in p.sources:
+                _bcheck(L.fdtdb_batch_add_source(self.h, c, int(s.box[0][0]), s.omega_c, s.width, s.amplitude))
+            for d in p.dfts:
+                om = _arr(d.omega)
+                _bcheck(L.fdtdb_batch_add_dft_flux(self.h, c, int(d.box[0][0]), len(om), _ptr(om)))
+            for e in p.energies:
+                _bcheck(L.fdtdb_batch_add_energy_monitor(self.h, c, int(e.box[0][0]), int(e.box[1][0]), e.every))
+        if tiling is not None:
+            _bcheck(L.fdtdb_batch_set_tiling(self.h, int(tiling[0]), int(tiling[1])))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fdtdb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tiling(self):
+        a, b = C.c_int(), C.c_int()
+        _bcheck(lib().fdtdb_batch_get_tiling(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def step(self, n: int):
+        _bcheck(lib().fdtdb_batch_step(self.h, int(n)))
+
+    def synchronize(self):
+        _bcheck(lib().fdtdb_batch_synchronize(self.h))
+
+    def field(self, cav: int, comp: int) -> np.ndarray:
+        out = np.zeros(int(self.ps[cav].n[0]), np.float64)
+        _bcheck(lib().fdtdb_batch_get_field(self.h, cav, comp, _ptr(out)))
+        return out
+
+    def flux(self, cav: int) -> np.ndarray:
+        nf = len(self.ps[cav].dfts[0].omega)
+        out = np.zeros(nf, np.float64)
+        _bcheck(lib().fdtdb_batch_dft_flux(self.h, cav, _ptr(out)))
+        return out
+
+    def energy(self, cav: int) -> np.ndarray:
+        n = C.c_int64()
+        _bcheck(lib().fdtdb_batch_energy(self.h, cav, None, 0, C.byref(n)))
+        out = np.zeros(3 * max(n.value, 1), np.float64)
+        _bcheck(lib().fdtdb_batch_energy(self.h, cav, _ptr(out), n.value, C.byref(n)))
+        return out[:3 * n.value].reshape(-1, 3)
