@@ -178,3 +178,28 @@ def config5_3d_large(nx: int = 512, ny: int = 512, steps: int = 4000, nb: int = 
     p.sources.append(gaussian_pulse(0, box(*xy, (42, 43)), profile=prof))
     p.dfts.append(DftFlux(2, box(*xy, (470, 471)), freq_grid(nfreq)))
     return p
+
+
+# ----------------------------------------------------------------------------------------------
+# learned closure: seeded initial weights (stream 5)
+# ----------------------------------------------------------------------------------------------
+CLOSURE_SHAPES = (("W1", (32, 7)), ("b1", (32,)), ("W2", (32, 32)), ("b2", (32,)), ("W3", (5, 32)), ("b3", (5,)))
+
+
+def closure_init(seed: int, hidden_scale: float = 0.3, state_scale: float = 0.0, force_scale: float = 0.0,
+                 width: int = 32) -> dict:
+    """Initial closure weights: hidden layers ~ N(0, hidden_scale^2); the output rows that update
+    the hidden state ~ N(0, state_scale^2) and the bath-force row ~ N(0, force_scale^2) (both zero
+    by default, which starts training from a quiet recurrence); output bias zero."""
+    rs = Stream(seed, 5)
+    shp = dict(CLOSURE_SHAPES)
+    shp["W1"], shp["b1"], shp["W2"], shp["b2"], shp["W3"] = (width, 7), (width,), (width, width), (width,), (5, width)
+    d = {}
+    for k in ("W1", "b1", "W2", "b2"):
+        d[k] = rs.normal(int(np.prod(shp[k]))).reshape(shp[k]) * hidden_scale
+    w3 = rs.normal(5 * width).reshape(5, width)
+    w3[:4] *= state_scale
+    w3[4] *= force_scale
+    d["W3"] = w3
+    d["b3"] = np.zeros(5)
+    return d

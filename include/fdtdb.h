@@ -130,6 +130,21 @@ fdtdb_status fdtdb_bath_params(int form, double omega0, double gamma0, int n_bat
                                double bath_gamma, double dephasing, double *omega_j, double *gamma_j,
                                double *k_j);
 
+/* Replace the explicit bath of Lorentz-Bath material `material_id` by the learned closure: per cell
+ * and E component a hidden state h (4 values, starting at zero) and the network
+ *   x = [E^{n+1/2} s_E, P^{n+1/2} s_P, (P^{n+1/2} - P^{n-1/2})/dt s_V, h]
+ *   z1 = tanh(W1 x + b1), z2 = tanh(W2 z1 + b2), o = W3 z2 + b3     (width 32)
+ *   h <- h + o[0:4];  the bath force term of eq:Pz_update-LB, (dt/2) sum_j k_j (a_j Y_j^n + b_j Y_j^{n-1}),
+ *   is replaced by o[4] / s_S, while A keeps the exact sum_j k_j c_j of the material's bath.
+ * weights: kClosureParams = 1477 floats, row major W1[32][7], b1[32], W2[32][32], b2[32], W3[5][32],
+ * b3[5] (copied).  scales: s_E, s_P, s_V, s_S (> 0).  FP32 network arithmetic.  Before the first
+ * step only (E_STATE).  E_INVALID unless width == 32 and the material is Lorentz-Bath. */
+fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *weights, int width,
+                                    const double *scales);
+
+/* Closure hidden state of one E component, [box cells][4] host doubles. */
+fdtdb_status fdtdb_get_closure_state(fdtdb_grid g, int material_id, int component, double *out);
+
 /* ---------------------------------------------------------------------------- sources, monitors */
 
 /* Soft current source on E component `component` over `box`:

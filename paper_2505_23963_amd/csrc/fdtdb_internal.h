@@ -16,6 +16,11 @@ constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
 // Update kind of a region.
 enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3 };
 
+// Learned bath closure: 7 inputs -> tanh(32) -> tanh(32) -> 5 outputs.  Weight layout (row major):
+// W1[32][7], b1[32], W2[32][32], b2[32], W3[5][32], b3[5].
+constexpr int kClosureWidth = 32;
+constexpr int kClosureParams = 32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5;
+
 // Curl axes of component c: (curl F)_c = d_{a1} F_{a2} - d_{a2} F_{a1}.
 __host__ __device__ constexpr int curl_a1(int c) { return c == 0 ? 1 : (c == 1 ? 2 : 0); }
 __host__ __device__ constexpr int curl_a2(int c) { return c == 0 ? 2 : (c == 1 ? 0 : 1); }
@@ -75,8 +80,9 @@ struct EArgs {
     const void *sigma;               // per material cell (storage type), or null
     double sigma0;
     const double *coef;              // FP64 coefficient table of the material
-    void *hid[3];                    // learned closure hidden state [mcells][4]
-    const float *cw;                 // learned closure weights (FP32)
+    void *hid[3];                    // learned closure hidden state [mcells] of float4
+    const float *cw;                 // learned closure weights (FP32, kClosureParams)
+    double cscale[4];                // closure input scales s_E, s_P, s_V and 1 / s_S
     // sources and clock
     const Clock *clock;
     int nsrc;

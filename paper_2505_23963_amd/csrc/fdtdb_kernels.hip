@@ -62,6 +62,51 @@ __device__ __forceinline__ double at_plus(const void *f, int q, int coord, int s
     return ok ? v : 0.0;
 }
 
+// tanh in FP32: odd Taylor series below |a| = 1/16, 1 - 2 / (1 + e^{2a}) above (absolute error
+// about 1e-7; saturates to +-1 for large |a|)
+__device__ __forceinline__ float tanh_f(float a) {
+    const float a2 = a * a;
+    const float small = a * (1.0f + a2 * (-1.0f / 3.0f + a2 * (2.0f / 15.0f)));
+    const float big = 1.0f - 2.0f / (1.0f + __expf(2.0f * a));
+    return fabsf(a) < 0.0625f ? small : big;
+}
+
+typedef const __attribute__((address_space(4))) float *cfptr;
+
+// The closure network on one input vector; weights are uniform over the launch and read through
+// the constant address space (scalar loads).  The empty asm statements keep the compiler from
+// hoisting every weight load to the top (which overflows the scalar register file): each unit's
+// row is loaded right before it is used.
+__device__ __forceinline__ void closure_mlp(cfptr w, const float *x, float *o) {
+    constexpr int W = kClosureWidth;
+    const cfptr W1 = w, b1 = W1 + W * 7, W2 = b1 + W, b2 = W2 + W * W, W3 = b2 + W, b3 = W3 + 5 * W;
+    float z1[W], z2[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        float s = b1[u];
+#pragma unroll
+        for (int v = 0; v < 7; ++v) s = fmaf(W1[u * 7 + v], x[v], s);
+        z1[u] = tanh_f(s);
+        if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        float s = b2[u];
+#pragma unroll
+        for (int v = 0; v < W; ++v) s = fmaf(W2[u * W + v], z1[v], s);
+        z2[u] = tanh_f(s);
+        __asm__ volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        float s = b3[u];
+#pragma unroll
+        for (int v = 0; v < W; ++v) s = fmaf(W3[u * W + v], z2[v], s);
+        o[u] = s;
+        __asm__ volatile("" ::: "memory");
+    }
+}
+
 // soft-current term dt J(t_n) profile / eps of component c at cell (i, j, k)
 __device__ __forceinline__ double source_term(const EArgs &a, const double *amp, int c, int i, int j, int k) {
     double s = 0.0;
@@ -205,6 +250,33 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                     ef += 0.5 / a.inv_eps * Eo * En;
                     const double v = V / a.dt;
                     ep += 0.5 * a.coef[2] * v * v;
+                }
+            } else if (KIND == K_CLOSURE) {
+                // Lorentz polarization with the bath force produced by the learned closure
+                T *Pc_ = static_cast<T *>(a.Pcur[c]);
+                T *Pn_ = static_cast<T *>(a.Pnew[c]);
+                const double Pc = (double)Pc_[m], Pp = (double)Pn_[m];
+                En = Eo + a.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
+                float4 *hp = static_cast<float4 *>(a.hid[c]) + m;
+                float4 hv = *hp;
+                const float x[7] = {(float)(En * a.cscale[0]), (float)(Pc * a.cscale[1]),
+                                    (float)((Pc - Pp) / a.dt * a.cscale[2]), hv.x, hv.y, hv.z, hv.w};
+                float o[5];
+                closure_mlp((cfptr)a.cw, x, o);
+                hv.x += o[0];
+                hv.y += o[1];
+                hv.z += o[2];
+                hv.w += o[3];
+                *hp = hv;
+                const double *cf = a.coef;
+                const double force = (double)o[4] * a.cscale[3];
+                const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - force * cf[5];
+                Pn_[m] = (T)Pnew;
+                if (ENERGY && sample) {
+                    ef += 0.5 / a.inv_eps * Eo * En;
+                    const double rho = cf[3] / sig;
+                    const double v = (Pc - Pp) / a.dt;
+                    ep += 0.5 * rho * (v * v + cf[4] * Pc * Pp);
                 }
             } else {  // K_BATH (NG == 0: plain Lorentz)
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
@@ -671,6 +743,7 @@ static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int n
         return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, ch, energy, s)
                    : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, ch, energy, s);
     if (kind == K_DRUDE) return launch_e_pml<DIM, T, K_DRUDE, 0, false>(a, ch, energy, s);
+    if (kind == K_CLOSURE) return launch_e_pml<DIM, T, K_CLOSURE, 0, false>(a, ch, energy, s);
     if (kind == K_BATH) {
         switch (ng) {
             case 0: return launch_e_pml<DIM, T, K_BATH, 0, false>(a, ch, energy, s);

@@ -70,6 +70,10 @@ struct Material {
     void *Y[2][3] = {};
     void *sigma_dev = nullptr;
     double *coef_dev = nullptr;
+    // learned closure
+    float *cw_dev = nullptr;
+    void *hid[3] = {};
+    double cscale[4] = {1.0, 1.0, 1.0, 1.0};
 };
 
 struct Region {
@@ -164,6 +168,17 @@ struct fdtdb_grid_s {
         if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(*p);
         return FDTDB_OK;
+    }
+    void release(void *&p) {
+        if (!p) return;
+        for (auto &q : allocs)
+            if (q == p) {
+                (void)hipFree(q);
+                q = allocs.back();
+                allocs.pop_back();
+                break;
+            }
+        p = nullptr;
     }
     size_t esize() const { return f64 ? 8 : 4; }
 };
@@ -363,6 +378,7 @@ void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh
         const Material &m = g->mats[r.mat];
         if (m.kind == K_DRUDE) e += 2.0 * ne * w;
         else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * w;
+        else if (m.kind == K_CLOSURE) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 2.0 * ne * 16.0;
     }
     *be = e;
     *bh = h;
@@ -529,13 +545,16 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             a.mcells = m.mcells;
             if (kind == K_DRUDE) {
                 for (int c = 0; c < 3; c++) a.Pcur[c] = m.P[0][c];
-            } else if (kind == K_BATH) {
+            } else if (kind == K_BATH || kind == K_CLOSURE) {
                 for (int c = 0; c < 3; c++) {
                     a.Pcur[c] = m.P[cur][c];
                     a.Pnew[c] = m.P[nxt][c];
                     a.Ycur[c] = m.Y[cur][c];
                     a.Ynew[c] = m.Y[nxt][c];
+                    a.hid[c] = m.hid[c];
                 }
+                a.cw = m.cw_dev;
+                for (int q = 0; q < 4; q++) a.cscale[q] = m.cscale[q];
             }
             a.sigma = m.sigma_per_cell ? m.sigma_dev : nullptr;
             a.sigma0 = m.sigma0;
@@ -837,6 +856,7 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
     m.coef[2] = (1.0 - 0.5 * gamma0 * dt - 0.5 * dt * skc) / A;
     m.coef[3] = 1.0 / w02;
     m.coef[4] = w02;
+    m.coef[5] = 1.0 / A;
     for (int jb = 0; jb < 4 * ng; jb++) {
         double *md = &m.coef[kCoefHead + kCoefMode * jb];
         md[0] = jb < n_bath ? aj[jb] : 0.0;
@@ -860,6 +880,44 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
             if (ng) TRY(g->alloc(&m.Y[lvl][c], words(mc * 4 * ng, g->f64)));
         }
     if (material_id) *material_id = (int)g->mats.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *weights, int width,
+                                    const double *scales) {
+    if (!g || !weights || !scales) return fail(FDTDB_E_INVALID, "null argument");
+    if (g->finalized) return fail(FDTDB_E_STATE, "closures must be set before the first step");
+    if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH)
+        return fail(FDTDB_E_INVALID, "the closure replaces the bath of a Lorentz-Bath material");
+    if (width != kClosureWidth) return fail(FDTDB_E_INVALID, "closure width must be %d", kClosureWidth);
+    for (int q = 0; q < 4; q++)
+        if (!(scales[q] > 0.0) || !std::isfinite(scales[q])) return fail(FDTDB_E_INVALID, "closure scales must be > 0");
+    for (int q = 0; q < kClosureParams; q++)
+        if (!std::isfinite(weights[q])) return fail(FDTDB_E_INVALID, "non-finite closure weight");
+    Material &m = g->mats[material_id];
+    if (!m.cw_dev) TRY(g->alloc((void **)&m.cw_dev, sizeof(float) * kClosureParams));
+    HIP_TRY(hipMemcpy(m.cw_dev, weights, sizeof(float) * kClosureParams, hipMemcpyHostToDevice));
+    for (int c = 0; c < 3; c++)
+        if (e_active(g->ndim, c) && !m.hid[c]) TRY(g->alloc(&m.hid[c], 16 * (size_t)m.mcells));
+    m.cscale[0] = scales[0];
+    m.cscale[1] = scales[1];
+    m.cscale[2] = scales[2];
+    m.cscale[3] = 1.0 / scales[3];
+    for (int lvl = 0; lvl < 2; lvl++)          // the explicit bath coordinates are no longer used
+        for (int c = 0; c < 3; c++) g->release(m.Y[lvl][c]);
+    m.kind = K_CLOSURE;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_get_closure_state(fdtdb_grid g, int material_id, int component, double *out) {
+    if (!g || !out || material_id < 0 || material_id >= (int)g->mats.size() || component < 0 || component > 2)
+        return fail(FDTDB_E_INVALID, "bad argument");
+    Material &m = g->mats[material_id];
+    if (m.kind != K_CLOSURE || !m.hid[component]) return fail(FDTDB_E_INVALID, "no closure state");
+    TRY(sync(g));
+    std::vector<float> tmp(4 * (size_t)m.mcells);
+    HIP_TRY(hipMemcpy(tmp.data(), m.hid[component], 16 * (size_t)m.mcells, hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < tmp.size(); q++) out[q] = tmp[q];
     return FDTDB_OK;
 }
 
@@ -1130,7 +1188,7 @@ fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out) {
         be += e * (double)r.cells();
         if (r.mat >= 0 && g->mats[r.mat].kind != K_BACKGROUND) {
             s.dispersive_cells += r.cells();
-            if (g->mats[r.mat].nb) s.bath_cells += r.cells();
+            if (g->mats[r.mat].nb && g->mats[r.mat].kind == K_BATH) s.bath_cells += r.cells();
         }
     }
     s.bytes_per_step_e = be;

@@ -61,6 +61,8 @@ SIGNATURES = [
                                          C.c_double, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]),
     ("fdtdb_bath_params", C.c_int, [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
                                     _dp, _dp, _dp]),
+    ("fdtdb_set_bath_closure", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_int, _dp]),
+    ("fdtdb_get_closure_state", C.c_int, [C.c_void_p, C.c_int, C.c_int, _dp]),
     ("fdtdb_add_source", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
                                    C.POINTER(C.c_int)]),
     ("fdtdb_add_dft_flux", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_int, _dp, C.POINTER(C.c_int)]),
@@ -139,6 +141,18 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
+CLOSURE_WIDTH = 32
+_CLOSURE_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def closure_weights(params: dict) -> np.ndarray:
+    """Flat FP32 closure weights in the library layout W1[32][7], b1, W2[32][32], b2, W3[5][32], b3."""
+    w = np.concatenate([np.asarray(params[k], np.float32).ravel() for k in _CLOSURE_ORDER])
+    if w.size != 32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5:
+        raise ValueError("closure weights must have width 32")
+    return w
+
+
 def bath_params(form: str, omega0: float, gamma0: float, n_bath: int, width: float, bath_gamma: float,
                 dephasing: float):
     """Table 1 map computed by the library."""
@@ -151,7 +165,9 @@ def bath_params(form: str, omega0: float, gamma0: float, n_bath: int, width: flo
 class Grid:
     """A device grid built from an fdtdb_inputs Problem description."""
 
-    def __init__(self, problem, stream: Optional[int] = None, graph_chunk: int = 0, dtype: Optional[str] = None):
+    def __init__(self, problem, stream: Optional[int] = None, graph_chunk: int = 0, dtype: Optional[str] = None,
+                 closures: Optional[dict] = None):
+        """closures: {material index: {"weights": 1477 floats, "scales": (s_E, s_P, s_V, s_S)}}."""
         L = lib()
         self.p = problem
         d = GridDesc()
@@ -189,6 +205,11 @@ class Grid:
             else:
                 raise TypeError(kind)
             self.mat_ids.append(mid.value)
+        for mi, cl in (closures or {}).items():
+            w = np.ascontiguousarray(cl["weights"], dtype=np.float32).ravel()
+            sc = _arr(cl["scales"])
+            _check(L.fdtdb_set_bath_closure(self.h, self.mat_ids[mi], w.ctypes.data_as(C.POINTER(C.c_float)), 32,
+                                            _ptr(sc)))
         for s in problem.sources:
             prof = _arr(s.profile)
             _check(L.fdtdb_add_source(self.h, s.comp, C.byref(_box(s.box)), s.omega_c, s.width, s.amplitude,
@@ -247,6 +268,11 @@ class Grid:
         out = np.zeros(nb * self._mcells(mi), np.float64)
         _check(lib().fdtdb_get_bath(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
         return out.reshape(nb, -1)
+
+    def closure_state(self, mi: int, comp: int) -> np.ndarray:
+        out = np.zeros(4 * self._mcells(mi), np.float64)
+        _check(lib().fdtdb_get_closure_state(self.h, self.mat_ids[mi], comp, _ptr(out)))
+        return out.reshape(-1, 4)
 
     def flux(self, mid: int, raw: bool = False):
         d = self.p.dfts[mid]
