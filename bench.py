@@ -147,7 +147,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the slab decomposition over several GPUs is described in DESIGN.md, not built)",
+              f"(a slab decomposition over several GPUs is designed but not built)",
               file=sys.stderr, flush=True)
         sys.exit(2)
     if args.copy_calibration:

@@ -203,3 +203,23 @@ def closure_init(seed: int, hidden_scale: float = 0.3, state_scale: float = 0.0,
     d["W3"] = w3
     d["b3"] = np.zeros(5)
     return d
+
+
+def closure_record(ntraj: int, nsteps: int, seed: int = 7, dt: float = 0.5):
+    """Synthetic recorder output for trainer tests: E and P, [nsteps][ntraj] float32, P starting
+    from rest.  Each trajectory is a smoothly switched-on, slowly decaying sinusoid with a random
+    frequency in [0.8, 1.2], phase and time constants (stream 5); E is a second such signal."""
+    rs = Stream(seed, 5)
+    u = rs.uniform(6 * ntraj).reshape(6, ntraj)
+    f = 0.8 + 0.4 * u[0]
+    ph = 6.283185307179586 * u[1]
+    tau = 20.0 + 40.0 * u[2]
+    fe = 0.8 + 0.4 * u[3]
+    phe = 6.283185307179586 * u[4]
+    amp = 0.5 + u[5]
+    t = (np.arange(nsteps) + 1.0)[:, None] * dt
+    env = (1.0 - np.exp(-t / tau)) * np.exp(-t / (4.0 * tau))
+    P = amp * np.sin(f * t + ph) * env
+    P -= np.sin(ph) * amp * env * np.exp(-t)          # no jump at the start
+    E = np.cos(fe * t + phe) * env
+    return E.astype(np.float32), P.astype(np.float32)

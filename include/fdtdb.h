@@ -297,6 +297,67 @@ fdtdb_status fdtdb_batch_energy(fdtdb_batch b, int cav, double *out, int64_t cap
 /* Last error message of the batch calls on this thread. */
 const char *fdtdb_batch_last_error(void);
 
+/* ------------------------------------------------------------------- learned-closure training data */
+/* Trajectory recorder on a Lorentz-Bath (or closure) material: for each step n < nsteps, row n of
+ * the record holds, at each chosen cell, E^{n+1/2} of `component` after the E update of step n and
+ * the new polarization P^{n+3/2} of that step (eq:Pz_update-LB), both rounded to FP32.  cells: n
+ * flat indices into the material's box (row major, z fastest; copied).  Before the first step only.
+ * The record is device memory owned by the grid: n * nsteps * 2 floats. */
+fdtdb_status fdtdb_add_probe(fdtdb_grid g, int material_id, int component, int n, const int64_t *cells,
+                             int64_t nsteps, int *probe_id);
+/* Copy the record out (synchronizes): E and P are [nsteps][n] floats, host buffers, or device
+ * buffers when to_device != 0. */
+fdtdb_status fdtdb_probe_data(fdtdb_grid g, int probe_id, float *E, float *P, int to_device);
+
+/* Closure trainer (the network of fdtdb_set_bath_closure).  The target along each recorded
+ * trajectory is the bath force of eq:Pz_update-LB, (dt/2) sum_j k_j (a_j Y_j^n + b_j Y_j^{n-1}),
+ * recomputed in FP64 by running eq:Yzj_finite_difference driven by the recorded P from rest.
+ * Inputs are scaled by 1/rms (s_E, s_P, s_V, s_S from the loaded record), the loss is the mean of
+ * (o[4] - S s_S)^2, gradients come from truncated backpropagation through time over windows of
+ * `window` steps taken in order from step 0 (the hidden state entering a window is carried from
+ * the previous window and held constant), and Adam (beta1 0.9, beta2 0.999, eps 1e-8) takes one
+ * step per window over all trajectories.  FP32 forward/backward, FP64 gradient sums and master
+ * weights. */
+typedef struct fdtdb_trainer_s *fdtdb_trainer;
+typedef struct {
+    int64_t ntraj;          /* trajectories N (recorded cells) */
+    int64_t nsteps;         /* recorded steps T per trajectory, a multiple of window */
+    int window;             /* truncated-BPTT window W, 1..4096 */
+    int activation;         /* 0: tanh (the closure); 1: identity (the linear special case) */
+    double dt;              /* time step */
+    int n_bath;             /* the explicit bath whose force is learned (arrays copied) */
+    const double *omega_j, *gamma_j, *k_j;
+    void *hip_stream;       /* borrowed; NULL = default stream */
+} fdtdb_trainer_desc;
+
+fdtdb_status fdtdb_trainer_create(const fdtdb_trainer_desc *desc, fdtdb_trainer *out);
+fdtdb_status fdtdb_trainer_destroy(fdtdb_trainer t);
+/* E, P: [nsteps][ntraj] floats as written by the recorder (host, or device if on_device != 0);
+ * copied.  Computes the FP64 targets, the scales and the packed inputs. */
+fdtdb_status fdtdb_trainer_load(fdtdb_trainer t, const float *E, const float *P, int on_device);
+/* s_E, s_P, s_V, s_S (4 doubles, host). */
+fdtdb_status fdtdb_trainer_get_scales(fdtdb_trainer t, double *scales);
+/* FP64 targets S, [nsteps][ntraj] doubles (host). */
+fdtdb_status fdtdb_trainer_get_targets(fdtdb_trainer t, double *S);
+/* Weights in the fdtdb_set_bath_closure layout (1477 floats, host; copied); resets Adam. */
+fdtdb_status fdtdb_trainer_set_weights(fdtdb_trainer t, const float *weights);
+fdtdb_status fdtdb_trainer_get_weights(fdtdb_trainer t, float *weights);
+/* Switch the activation used by training.  Going from identity (1) to tanh (0) with weights set,
+ * the weights are first rescaled so that the tanh network computes the identity network's
+ * function to O(eps^2) (W1, b1, b2 times eps, W3 divided by eps: every pre-activation shrinks by
+ * eps, where tanh is linear); Adam's moments restart.  This carries a closure trained in the
+ * linear regime (the bath is a linear filter of the polarization history, eq:EOM_LorentzBath-2)
+ * into the tanh network.  eps in (0, 1]. */
+fdtdb_status fdtdb_trainer_set_activation(fdtdb_trainer t, int activation, double eps);
+/* Loss and gradient at the current weights without updating them: the mean over windows of the
+ * window loss and of its gradient (1477 doubles, host). */
+fdtdb_status fdtdb_trainer_loss_grad(fdtdb_trainer t, double *loss, double *grad);
+/* `epochs` passes over the record, learning rate lr * lr_decay^epoch; the mean window loss of
+ * each epoch (taken before each window's update) goes to loss_per_epoch[epochs] (may be NULL). */
+fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double lr_decay, double *loss_per_epoch);
+/* Last error message of the trainer calls on this thread. */
+const char *fdtdb_trainer_last_error(void);
+
 /* Last error message on this thread ("" if none). */
 const char *fdtdb_last_error(void);
 

@@ -137,3 +137,45 @@ def bath_force(P: np.ndarray, dt: float, wj, gj, kj) -> np.ndarray:
         Ym, Y0 = Y0, Yn
         Pm = P[:, m]
     return S
+
+
+def prepare(E: np.ndarray, P: np.ndarray, dt: float, wj, gj, kj):
+    """Training inputs from a recorder's output.
+
+    E, P: [T, N] with row n = E^{n+1/2} and the new P^{n+3/2} of step n, starting from rest.
+    Returns X [N, T, 3] (scaled E, P, V at each step's input), Y [N, T] (scaled bath force),
+    scales (s_E, s_P, s_V, s_S) = 1 / rms of each, and the unscaled force S [N, T].
+    """
+    E = np.asarray(E, np.float64).T
+    Pn = np.asarray(P, np.float64).T
+    N, T = E.shape
+    Pfull = np.concatenate([np.zeros((N, 1)), Pn], axis=1)        # P^{1/2} = 0 ... P^{T+1/2}
+    S = bath_force(Pfull, dt, wj, gj, kj)
+    Pin = Pfull[:, :T]                                              # the P entering step n
+    Pprev = np.concatenate([np.zeros((N, 1)), Pfull[:, :T - 1]], axis=1)
+    V = (Pin - Pprev) / dt
+
+    def inv_rms(a):
+        r = np.sqrt(np.mean(a * a))
+        return 1.0 / r if r > 0 else 1.0
+
+    sc = np.array([inv_rms(E), inv_rms(Pin), inv_rms(V), inv_rms(S)])
+    X = np.stack([E * sc[0], Pin * sc[1], V * sc[2]], axis=2)
+    return X, S * sc[3], sc, S
+
+
+def tbptt_loss_grad(p: dict, X, Y, window: int, act="tanh"):
+    """Truncated BPTT over consecutive windows from step 0: the hidden state entering window c
+    is the forward state at its first step (held constant); returns the mean over windows of the
+    window loss and of its gradient."""
+    N, T, _ = X.shape
+    _, h, _ = forward(p, X, np.zeros((N, K)), act)
+    nwin = T // window
+    Ls, G = 0.0, {k: np.zeros_like(v) for k, v in p.items()}
+    for c in range(nwin):
+        sl = slice(c * window, (c + 1) * window)
+        L, g = loss_and_grad(p, X[:, sl], Y[:, sl], h[:, c * window], act)
+        Ls += L / nwin
+        for k in G:
+            G[k] += g[k] / nwin
+    return Ls, G

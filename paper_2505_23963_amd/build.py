@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtdb.so")
-SOURCES = ["fdtdb_kernels.hip", "fdtdb_runtime.hip", "fdtdb_batch.hip"]
+SOURCES = ["fdtdb_kernels.hip", "fdtdb_runtime.hip", "fdtdb_batch.hip", "fdtdb_train.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

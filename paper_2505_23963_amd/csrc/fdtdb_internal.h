@@ -21,6 +21,17 @@ enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3 };
 constexpr int kClosureWidth = 32;
 constexpr int kClosureParams = 32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5;
 
+// tanh in FP32: odd Taylor series below |a| = 1/16 (no transcendental; a wave whose lanes are all
+// in range skips the exponential), 1 - 2 / (1 + e^{2a}) above (absolute error about 1e-7;
+// saturates to +-1 for large |a|).  Shared by closure inference and training.
+__device__ __forceinline__ float tanh_f(float a) {
+    if (fabsf(a) < 0.0625f) {
+        const float a2 = a * a;
+        return a * (1.0f + a2 * (-1.0f / 3.0f + a2 * (2.0f / 15.0f)));
+    }
+    return 1.0f - 2.0f / (1.0f + __expf(2.0f * a));
+}
+
 // Curl axes of component c: (curl F)_c = d_{a1} F_{a2} - d_{a2} F_{a1}.
 __host__ __device__ constexpr int curl_a1(int c) { return c == 0 ? 1 : (c == 1 ? 2 : 0); }
 __host__ __device__ constexpr int curl_a2(int c) { return c == 0 ? 2 : (c == 1 ? 0 : 1); }

@@ -62,15 +62,6 @@ __device__ __forceinline__ double at_plus(const void *f, int q, int coord, int s
     return ok ? v : 0.0;
 }
 
-// tanh in FP32: odd Taylor series below |a| = 1/16, 1 - 2 / (1 + e^{2a}) above (absolute error
-// about 1e-7; saturates to +-1 for large |a|)
-__device__ __forceinline__ float tanh_f(float a) {
-    const float a2 = a * a;
-    const float small = a * (1.0f + a2 * (-1.0f / 3.0f + a2 * (2.0f / 15.0f)));
-    const float big = 1.0f - 2.0f / (1.0f + __expf(2.0f * a));
-    return fabsf(a) < 0.0625f ? small : big;
-}
-
 typedef const __attribute__((address_space(4))) float *cfptr;
 
 // The closure network on one input vector; weights are uniform over the launch and read through
@@ -709,6 +700,17 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *f, long long n, i
     }
 }
 
+// trajectory recorder: row n of the record = step n (steps beyond the capacity are not recorded)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probe(const T *E, const T *P, const int *q, const int *m, int n,
+                                                  const Clock *clk, long long capacity, float *outE, float *outP) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const long long row = clk->step;
+    if (i >= n || row >= capacity) return;
+    outE[row * n + i] = (float)E[q[i]];
+    outP[row * n + i] = (float)P[m[i]];
+}
+
 // ---------------------------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------------------------
@@ -759,6 +761,17 @@ static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int n
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_probe(bool f64, const void *E, const void *P, const int *q, const int *m, int n, const Clock *clk,
+                        long long capacity, float *outE, float *outP, hipStream_t s) {
+    if (f64)
+        hipLaunchKernelGGL(k_probe<double>, dim3(nblocks(n)), dim3(kBlock), 0, s, (const double *)E, (const double *)P, q,
+                           m, n, clk, capacity, outE, outP);
+    else
+        hipLaunchKernelGGL(k_probe<float>, dim3(nblocks(n)), dim3(kBlock), 0, s, (const float *)E, (const float *)P, q, m,
+                           n, clk, capacity, outE, outP);
+    return hipGetLastError();
 }
 
 hipError_t launch_update_e(int dim, bool f64, const EArgs &a, const double *coef_host, int kind, int ng, bool pml,

@@ -27,6 +27,8 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
                             const double *stage, int npts, double2 *acc, hipStream_t s);
 hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s);
 hipError_t launch_nonfinite(bool f64, const void *f, long long n, int *flag, hipStream_t s);
+hipError_t launch_probe(bool f64, const void *E, const void *P, const int *q, const int *m, int n, const Clock *clk,
+                        long long capacity, float *outE, float *outP, hipStream_t s);
 }  // namespace fdtdb
 
 using namespace fdtdb;
@@ -121,6 +123,15 @@ struct Energy {
     long long capacity = 0;
 };
 
+// trajectory recorder: E^{n+1/2} and the new P^{n+3/2} at chosen cells of one material, steps
+// [0, capacity)
+struct Probe {
+    int mat, comp, n;
+    long long capacity;
+    int *q = nullptr, *m = nullptr;      // grid and material-box indices of the cells
+    float *E = nullptr, *P = nullptr;    // [capacity][n]
+};
+
 size_t words(long long n, bool f64) { return (size_t)n * (f64 ? 8 : 4); }
 
 }  // namespace
@@ -139,6 +150,7 @@ struct fdtdb_grid_s {
     std::vector<Source> srcs;
     std::vector<Dft> dfts;
     std::vector<Energy> ens;
+    std::vector<Probe> probes;
     std::vector<Region> regions;    // E / material update regions
     std::vector<Region> hregions;   // H update regions (CPML partition only)
     double *pml_b[3] = {}, *pml_c[3] = {}, *pml_bh[3] = {}, *pml_ch[3] = {};
@@ -597,6 +609,9 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     }
     for (auto &e : g->ens)
         HIP_TRY(launch_energy_reduce(g->clock, e.partial, e.nslots, e.every, e.out, e.capacity, g->stream));
+    for (auto &pr : g->probes)
+        HIP_TRY(launch_probe(g->f64, g->E[pr.comp], g->mats[pr.mat].P[nxt][pr.comp], pr.q, pr.m, pr.n, g->clock,
+                             pr.capacity, pr.E, pr.P, g->stream));
     for (auto &r : g->hregions) {
         HArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
@@ -1019,6 +1034,52 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
     e.every = every;
     g->ens.push_back(e);
     if (monitor_id) *monitor_id = (int)g->ens.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_add_probe(fdtdb_grid g, int material_id, int component, int n, const int64_t *cells,
+                             int64_t nsteps, int *probe_id) {
+    if (!g || !cells) return fail(FDTDB_E_INVALID, "null argument");
+    if (g->finalized) return fail(FDTDB_E_STATE, "probes must be added before the first step");
+    if (material_id < 0 || material_id >= (int)g->mats.size()) return fail(FDTDB_E_INVALID, "bad material");
+    Material &mt = g->mats[material_id];
+    if (mt.kind != K_BATH && mt.kind != K_CLOSURE) return fail(FDTDB_E_INVALID, "probes record Lorentz-Bath cells");
+    if (component < 0 || component > 2 || !e_active(g->ndim, component)) return fail(FDTDB_E_INVALID, "bad component");
+    if (n < 1 || nsteps < 1) return fail(FDTDB_E_INVALID, "need n >= 1 cells and nsteps >= 1");
+    Probe p;
+    p.mat = material_id;
+    p.comp = component;
+    p.n = n;
+    p.capacity = nsteps;
+    std::vector<int> q(n), m(n);
+    for (int i = 0; i < n; i++) {
+        if (cells[i] < 0 || cells[i] >= mt.mcells) return fail(FDTDB_E_INVALID, "probe cell %d outside the material", i);
+        const long long c = cells[i];
+        const long long ii = c / ((long long)mt.mext[1] * mt.mext[2]);
+        const long long rem = c - ii * mt.mext[1] * mt.mext[2];
+        const long long jj = rem / mt.mext[2], kk = rem - jj * mt.mext[2];
+        q[i] = (int)(((mt.lo[0] + ii) * g->n[1] + (mt.lo[1] + jj)) * g->n[2] + (mt.lo[2] + kk));
+        m[i] = (int)c;
+    }
+    TRY(g->alloc((void **)&p.q, 4 * (size_t)n));
+    TRY(g->alloc((void **)&p.m, 4 * (size_t)n));
+    TRY(g->alloc((void **)&p.E, 4 * (size_t)n * (size_t)nsteps));
+    TRY(g->alloc((void **)&p.P, 4 * (size_t)n * (size_t)nsteps));
+    HIP_TRY(hipMemcpy(p.q, q.data(), 4 * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p.m, m.data(), 4 * (size_t)n, hipMemcpyHostToDevice));
+    g->probes.push_back(p);
+    if (probe_id) *probe_id = (int)g->probes.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_probe_data(fdtdb_grid g, int probe_id, float *E, float *P, int to_device) {
+    if (!g || !E || !P || probe_id < 0 || probe_id >= (int)g->probes.size()) return fail(FDTDB_E_INVALID, "bad argument");
+    TRY(sync(g));
+    const Probe &p = g->probes[probe_id];
+    const size_t bytes = 4 * (size_t)p.n * (size_t)p.capacity;
+    const hipMemcpyKind k = to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpy(E, p.E, bytes, k));
+    HIP_TRY(hipMemcpy(P, p.P, bytes, k));
     return FDTDB_OK;
 }
 

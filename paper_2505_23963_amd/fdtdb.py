@@ -98,6 +98,20 @@ SIGNATURES = [
     ("fdtdb_batch_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp]),
     ("fdtdb_batch_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
     ("fdtdb_batch_last_error", C.c_char_p, []),
+    ("fdtdb_add_probe", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64), C.c_int64,
+                                  C.POINTER(C.c_int)]),
+    ("fdtdb_probe_data", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
+    ("fdtdb_trainer_create", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("fdtdb_trainer_destroy", C.c_int, [C.c_void_p]),
+    ("fdtdb_trainer_load", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("fdtdb_trainer_get_scales", C.c_int, [C.c_void_p, _dp]),
+    ("fdtdb_trainer_get_targets", C.c_int, [C.c_void_p, _dp]),
+    ("fdtdb_trainer_set_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    ("fdtdb_trainer_get_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    ("fdtdb_trainer_set_activation", C.c_int, [C.c_void_p, C.c_int, C.c_double]),
+    ("fdtdb_trainer_loss_grad", C.c_int, [C.c_void_p, _dp, _dp]),
+    ("fdtdb_trainer_train", C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double, _dp]),
+    ("fdtdb_trainer_last_error", C.c_char_p, []),
     ("fdtdb_last_error", C.c_char_p, []),
     ("fdtdb_version", C.c_char_p, []),
 ]
@@ -182,6 +196,7 @@ class Grid:
         d.pml_R0 = problem.pml_R0
         d.hip_stream = stream
         h = C.c_void_p()
+        self._probes = {}
         _check(L.fdtdb_create_grid(C.byref(d), C.byref(h)))
         self.h = h
         self.mat_ids = []
@@ -268,6 +283,23 @@ class Grid:
         out = np.zeros(nb * self._mcells(mi), np.float64)
         _check(lib().fdtdb_get_bath(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
         return out.reshape(nb, -1)
+
+    def add_probe(self, mi: int, comp: int, cells, nsteps: int) -> int:
+        """Record E^{n+1/2} and the new P at material-box cells for steps [0, nsteps)."""
+        c = np.ascontiguousarray(cells, np.int64)
+        pid = C.c_int(-1)
+        _check(lib().fdtdb_add_probe(self.h, self.mat_ids[mi], comp, len(c), c.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     int(nsteps), C.byref(pid)))
+        self._probes[pid.value] = (len(c), int(nsteps))
+        return pid.value
+
+    def probe_data(self, pid: int):
+        """(E, P) records, [nsteps][ncells] float32 host arrays."""
+        n, T = self._probes[pid]
+        E = np.zeros((T, n), np.float32)
+        P = np.zeros((T, n), np.float32)
+        _check(lib().fdtdb_probe_data(self.h, pid, E.ctypes.data, P.ctypes.data, 0))
+        return E, P
 
     def closure_state(self, mi: int, comp: int) -> np.ndarray:
         out = np.zeros(4 * self._mcells(mi), np.float64)
@@ -403,3 +435,85 @@ class Batch:
         out = np.zeros(3 * max(n.value, 1), np.float64)
         _bcheck(lib().fdtdb_batch_energy(self.h, cav, _ptr(out), n.value, C.byref(n)))
         return out[:3 * n.value].reshape(-1, 3)
+
+
+class TrainerDesc(C.Structure):
+    _fields_ = [("ntraj", C.c_int64), ("nsteps", C.c_int64), ("window", C.c_int), ("activation", C.c_int),
+                ("dt", C.c_double), ("n_bath", C.c_int), ("omega_j", _dp), ("gamma_j", _dp), ("k_j", _dp),
+                ("hip_stream", C.c_void_p)]
+
+
+def _tcheck(st: int):
+    if st != OK:
+        raise FdtdbError(st, lib().fdtdb_trainer_last_error().decode())
+
+
+class Trainer:
+    """GPU trainer of the learned closure (fdtdb_trainer_* entry points)."""
+
+    def __init__(self, ntraj: int, nsteps: int, window: int, dt: float, omega_j, gamma_j, k_j,
+                 activation: str = "tanh", stream: Optional[int] = None):
+        L = lib()
+        self._bath = [_arr(omega_j), _arr(gamma_j), _arr(k_j)]
+        d = TrainerDesc()
+        d.ntraj, d.nsteps, d.window = int(ntraj), int(nsteps), int(window)
+        d.activation = {"tanh": 0, "identity": 1}[activation]
+        d.dt = float(dt)
+        d.n_bath = len(self._bath[0])
+        d.omega_j, d.gamma_j, d.k_j = (_ptr(a) for a in self._bath)
+        d.hip_stream = stream
+        h = C.c_void_p()
+        _tcheck(L.fdtdb_trainer_create(C.byref(d), C.byref(h)))
+        self.h = h
+        self.N, self.T = int(ntraj), int(nsteps)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fdtdb_trainer_destroy(self.h)
+            self.h = None
+
+    def load(self, E: np.ndarray, P: np.ndarray):
+        """E, P: [nsteps][ntraj] records (float32)."""
+        E = np.ascontiguousarray(E, np.float32)
+        P = np.ascontiguousarray(P, np.float32)
+        if E.shape != (self.T, self.N) or P.shape != (self.T, self.N):
+            raise ValueError("records must be [nsteps][ntraj]")
+        _tcheck(lib().fdtdb_trainer_load(self.h, E.ctypes.data, P.ctypes.data, 0))
+
+    def load_from_grid(self, grid: "Grid", pid: int):
+        E, P = grid.probe_data(pid)
+        self.load(E, P)
+
+    def scales(self) -> np.ndarray:
+        out = np.zeros(4, np.float64)
+        _tcheck(lib().fdtdb_trainer_get_scales(self.h, _ptr(out)))
+        return out
+
+    def targets(self) -> np.ndarray:
+        out = np.zeros((self.T, self.N), np.float64)
+        _tcheck(lib().fdtdb_trainer_get_targets(self.h, _ptr(out)))
+        return out
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32).ravel()
+        _tcheck(lib().fdtdb_trainer_set_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5, np.float32)
+        _tcheck(lib().fdtdb_trainer_get_weights(self.h, w.ctypes.data_as(C.POINTER(C.c_float))))
+        return w
+
+    def set_activation(self, activation: str, eps: float = 1e-4):
+        """Switch the training activation; identity -> tanh carries the weights over (eps scaling)."""
+        _tcheck(lib().fdtdb_trainer_set_activation(self.h, {"tanh": 0, "identity": 1}[activation], float(eps)))
+
+    def loss_grad(self):
+        loss = np.zeros(1, np.float64)
+        g = np.zeros(32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5, np.float64)
+        _tcheck(lib().fdtdb_trainer_loss_grad(self.h, _ptr(loss), _ptr(g)))
+        return float(loss[0]), g
+
+    def train(self, epochs: int, lr: float, lr_decay: float = 1.0) -> np.ndarray:
+        out = np.zeros(max(int(epochs), 1), np.float64)
+        _tcheck(lib().fdtdb_trainer_train(self.h, int(epochs), float(lr), float(lr_decay), _ptr(out)))
+        return out[:int(epochs)]

@@ -119,3 +119,43 @@ def test_training_fits_one_mode_bath():
         cl.adam_step(p, g, m, v, it, lr=3e-3 * 0.995 ** it)
     L1 = cl.loss(p, X, Y, h0, "identity")
     assert L0 > 0.5 and L1 < 1e-3
+
+
+def test_tbptt_one_window_is_bptt_and_windows_carry_state():
+    """With one window TBPTT is plain BPTT; with several, the loss is the mean of the window losses
+    of one uninterrupted forward pass (the carried state is the forward state)."""
+    rng = np.random.default_rng(4)
+    p = _params(8, rng)
+    X = rng.normal(size=(3, 12, 3))
+    Y = rng.normal(size=(3, 12))
+    L1, g1 = cl.tbptt_loss_grad(p, X, Y, 12)
+    L0, g0 = cl.loss_and_grad(p, X, Y, np.zeros((3, 4)))
+    assert abs(L1 - L0) < 1e-15 and np.max(np.abs(cl.flatten(g1) - cl.flatten(g0))) < 1e-15
+    L3, _ = cl.tbptt_loss_grad(p, X, Y, 4)
+    assert abs(L3 - L0) < 1e-13 * L0          # equal-length windows: same mean squared error
+
+
+def test_prepare_rebuilds_the_inputs_of_the_polarization_update(oracle_lib):
+    """prepare() on the C oracle's recorded trajectory: V is the P difference entering each step,
+    and the force closes eq:Pz_update-LB with the recorded E (as in the bath-force pin)."""
+    wj, gj, kj = np.array([0.95, 1.1]), np.array([0.02, 0.01]), np.array([0.1, 0.15])
+    w0, g0, sig = 1.0, 0.0, 0.05
+    p = Problem(name="0d", ndim=1, n=(1, 1, 1), bc=(PERIODIC, PERIODIC, PERIODIC), dtype="f64")
+    p.materials.append(LorentzBath(box((0, 1)), omega0=w0, gamma0=g0, eps_inf=1.0, sigma=sig, n_bath=2, omega_j=wj,
+                                   gamma_j=gj, k_j=kj))
+    o = oracle_lib.Oracle(p)
+    n = np.arange(200)
+    E = np.exp(-((n - 30) / 6.0) ** 2) * np.cos(1.0 * n * DT)
+    Pn = o.drive(0, 2, E)
+    X, Y, sc, S = cl.prepare(E[:, None], Pn[:, None], DT, wj, gj, kj)
+    Pin = X[0, :, 1] / sc[1]
+    V = X[0, :, 2] / sc[2]
+    assert np.allclose(Pin[1:], Pn[:-1], rtol=0, atol=1e-15) and Pin[0] == 0.0
+    assert np.allclose(V[1:] * DT, np.diff(np.concatenate([[0.0], Pn[:-1]])), rtol=0, atol=1e-15)
+    skc = np.sum(kj * kj * DT / (2 * (1 + 0.5 * gj * DT)))
+    A = 1 + 0.5 * g0 * DT + 0.5 * DT * skc
+    Pm1 = Pin - V * DT
+    rhs = (w0 ** 2 * DT ** 2 * sig * E - (w0 ** 2 * DT ** 2 - 2) * Pin - (1 - 0.5 * g0 * DT - 0.5 * DT * skc) * Pm1
+           - S[0]) / A
+    assert np.max(np.abs(rhs - Pn)) < 1e-14 * np.max(np.abs(Pn))
+    assert abs(np.sqrt(np.mean((Y[0] / sc[3]) ** 2)) * sc[3] - 1.0) < 1e-12
