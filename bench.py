@@ -133,6 +133,86 @@ def bench_cavities(args):
     }), flush=True)
 
 
+def bench_closure2d(args):
+    """Learned closure vs explicit N_b = 64 bath on the 2D 2048^2 TM grid with a 1024^2 Lorentzian-bath
+    patch: cell-updates/s of both, and the errors against the explicit run."""
+    import numpy as np
+    import torch
+    from fdtdb_inputs import configs
+    from fdtdb_inputs.philox import Stream
+    from fdtdb_inputs.problem import LorentzBath
+    from paper_2505_23963_amd import Grid, closure
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    s = stream.cuda_stream
+    # training data: the same material on a 256^2 grid, 8192 recorded cells, 1024 steps
+    rec = configs.config4_2d(n=256, patch=(64, 192), src_x=56, flux_x=208)
+    cells = np.unique(Stream(1004, 5).integers(11000, 0, 128 * 128 - 1))[:8192]
+    t0 = time.perf_counter()
+    E, P = closure.record(rec, 0, 2, cells, 1024, stream=s)
+    res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), stream=s)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] closure trained in {t_train:.1f} s: loss {res['loss_tanh']:.3e}", file=sys.stderr, flush=True)
+    p = configs.config4_2d()
+    steps = args.steps if args.steps != 64 else 2000
+
+    def timed(closures=None, prob=None):
+        g = Grid(prob or p, stream=s, closures=closures)
+        g.step(args.warmup)
+        g.synchronize()
+        g.set_profiling(True)
+        g.kernel_records()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(steps)
+        g.synchronize()
+        dt = time.perf_counter() - t
+        recs = g.kernel_records()
+        lb = max((r for r in recs if r["phase"] == 0), key=lambda r: r["ms_total"])
+        return p.cells * steps / dt / 1e9, dt / steps * 1e3, lb["ms_total"] / max(lb["launches"], 1), g
+
+    v_exp, ms_exp, k_exp, _ = timed()
+    cl = {0: {"weights": res["weights"], "scales": res["scales"]}}
+    v_cl, ms_cl, k_cl, _ = timed(cl)
+    # accuracy over the workload's 10000 steps (and before the explicit bath's revival)
+    out_err = {}
+    for horizon in (2500, 10000):
+        fe = Grid(p, stream=s)
+        fe.step(horizon)
+        ref_f, ref_e = fe.flux(0), fe.field(2)
+        del fe
+        runs = {"closure": (p, cl)}
+        pl = configs.config4_2d()
+        m = pl.materials[0]
+        pl.materials[0] = LorentzBath(m.box, omega0=m.omega0, gamma0=m.gamma0 + m.dephasing, eps_inf=m.eps_inf,
+                                      sigma=m.sigma, n_bath=0)
+        runs["lorentz_gamma0_plus_dephasing"] = (pl, None)
+        runs["explicit_nb2"] = (configs.config4_2d(nb=2), None)
+        for name, (pp, c) in runs.items():
+            g = Grid(pp, stream=s, closures=c)
+            g.step(horizon)
+            f, e = g.flux(0), g.field(2)
+            nf = float(np.max(np.abs(ref_f)))
+            out_err.setdefault(name, {})[str(horizon)] = {
+                "spectral": float(np.max(np.abs(f - ref_f)) / nf) if nf > 0 else None,
+                "field": float(np.linalg.norm(e - ref_e) / np.linalg.norm(ref_e))}
+            del g
+    print(json.dumps({
+        "metric": METRIC, "value": round(v_cl, 4), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_cl, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2D TM 2048x2048, PML 32, 1024x1024 Lorentzian-bath patch (N_b=64 explicit vs "
+                               "K=4 learned closure), line source, 256-frequency flux line", "cells": p.cells},
+        "explicit": {"value": round(v_exp, 4), "ms_per_step": round(ms_exp, 4), "patch_kernel_ms": round(k_exp, 4)},
+        "learned": {"value": round(v_cl, 4), "ms_per_step": round(ms_cl, 4), "patch_kernel_ms": round(k_cl, 4)},
+        "learned_over_explicit": round(v_cl / v_exp, 3),
+        "training": {"seconds": round(t_train, 2), "loss_linear": res["loss_linear"], "loss_tanh": res["loss_tanh"],
+                     "trajectories": res["trajectories"], "steps": 1024, "window": 64,
+                     "adam_steps": len(res["curve"]) * res["windows_per_epoch"]},
+        "errors_vs_explicit": out_err,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,8 +222,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--workload", choices=["planar3d", "cavities"], default="planar3d",
-                    help="planar3d: the default 256x256x512 line; cavities: the 64-cavity batched 1D workload")
+    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d"], default="planar3d",
+                    help="planar3d: the default 256x256x512 line; cavities: the 64-cavity batched 1D workload; "
+                         "closure2d: learned closure vs explicit bath on the 2D 2048^2 grid")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -155,6 +236,9 @@ def main():
         return
     if args.workload == "cavities":
         bench_cavities(args)
+        return
+    if args.workload == "closure2d":
+        bench_closure2d(args)
         return
 
     import torch

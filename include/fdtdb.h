@@ -353,7 +353,10 @@ fdtdb_status fdtdb_trainer_set_activation(fdtdb_trainer t, int activation, doubl
  * window loss and of its gradient (1477 doubles, host). */
 fdtdb_status fdtdb_trainer_loss_grad(fdtdb_trainer t, double *loss, double *grad);
 /* `epochs` passes over the record, learning rate lr * lr_decay^epoch; the mean window loss of
- * each epoch (taken before each window's update) goes to loss_per_epoch[epochs] (may be NULL). */
+ * each epoch (taken before each window's update) goes to loss_per_epoch[epochs] (may be NULL).
+ * An epoch whose loss is not finite or exceeds 100 times the best so far (the learned recurrence
+ * ran away) is undone (weights and Adam state restored) and repeated at half the rate; after 12
+ * such retries the call returns FDTDB_E_DIVERGED. */
 fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double lr_decay, double *loss_per_epoch);
 /* Last error message of the trainer calls on this thread. */
 const char *fdtdb_trainer_last_error(void);

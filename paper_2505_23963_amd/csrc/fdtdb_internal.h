@@ -72,6 +72,17 @@ struct EnergyDev {
 };
 
 // Arguments of the E / material update of one region.
+// One region of a grouped launch: several background regions updated by one kernel launch, the
+// blocks of region r being [block0, next block0).
+struct RegionDesc {
+    int lo[3], ext[3];
+    int ext12;
+    int block0;
+    double inv_eps;
+    void *psi[3][2];
+};
+constexpr int kMaxGroup = 32;
+
 struct EArgs {
     void *E[3];
     const void *H[3];
@@ -102,6 +113,8 @@ struct EArgs {
     int nen;
     EnergyDev en[kMaxEnergy];
     long long block_base;            // first partial slot of this launch
+    const RegionDesc *rd;            // grouped launch: region table (nrd > 0), else the box above
+    int nrd;
 };
 
 struct HArgs {
@@ -114,6 +127,8 @@ struct HArgs {
     double dt;
     void *psi[3][2];
     const double *pml_b[3], *pml_c[3];
+    const RegionDesc *rd;            // grouped launch: region table (nrd > 0)
+    int nrd;
 };
 
 struct DftArgs {

@@ -149,6 +149,43 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + l;
 }
 
+// the region a block of a launch works on: the launch's own box, or (grouped launch) the entry of
+// the region table that holds the block; returns the block index within the region
+struct RegV {
+    int lo[3], ext[3], ext12;
+    double inv_eps;
+    void *psi[3][2];
+};
+template <class A>
+__device__ __forceinline__ int pick_region(const A &a, double inv_eps, int b, RegV &R) {
+    if (a.nrd > 0) {
+        int r = 0;
+        for (int s = 1; s < kMaxGroup; ++s)
+            if (s < a.nrd && b >= a.rd[s].block0) r = s;
+        const RegionDesc &D = a.rd[r];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            R.lo[x] = D.lo[x];
+            R.ext[x] = D.ext[x];
+            R.psi[x][0] = D.psi[x][0];
+            R.psi[x][1] = D.psi[x][1];
+        }
+        R.ext12 = D.ext12;
+        R.inv_eps = D.inv_eps;
+        return b - D.block0;
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        R.lo[x] = a.lo[x];
+        R.ext[x] = a.ext[x];
+        R.psi[x][0] = a.psi[x][0];
+        R.psi[x][1] = a.psi[x][1];
+    }
+    R.ext12 = a.ext12;
+    R.inv_eps = inv_eps;
+    return b;
+}
+
 // 4-wide native vectors for non-temporal (streaming) loads and stores
 typedef float nv4f __attribute__((ext_vector_type(4)));
 typedef double nv4d __attribute__((ext_vector_type(4)));
@@ -178,8 +215,9 @@ __device__ __forceinline__ void unflatten(int t, const int *lo, const int *ext, 
 template <int DIM, typename T, int KIND, int NG, bool PML, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     using V4 = vec4_t<T>;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const bool live = t < a.ext[0] * a.ext12;
+    RegV R;
+    const int t = pick_region(a, a.inv_eps, xcd_block(blockIdx.x, gridDim.x), R) * kBlock + threadIdx.x;
+    const bool live = t < R.ext[0] * R.ext12;
     double ef = 0.0, ep = 0.0, eb = 0.0;   // energy densities of this cell (when sampled)
     bool sample = false;
     if (ENERGY) {
@@ -190,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     if (live) {
         double amp[kMaxSources];
         load_amps(a, amp);
-        unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
+        unflatten<DIM>(t, R.lo, R.ext, R.ext12, i, j, k);
         const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
         const int q = i * s0 + j * s1 + k;
         const int coord[3] = {i, j, k};
@@ -211,14 +249,14 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
             if (axis_live(DIM, a2) && h_active(DIM, a1))
                 t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
             if (PML) {
-                if (a.psi[c][0]) {
-                    T *ps = static_cast<T *>(a.psi[c][0]);
+                if (R.psi[c][0]) {
+                    T *ps = static_cast<T *>(R.psi[c][0]);
                     const double psi = a.pml_b[a1][coord[a1]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a1][coord[a1]] * t1;
                     __builtin_nontemporal_store((T)psi, ps + t);
                     t1 += psi;
                 }
-                if (a.psi[c][1]) {
-                    T *ps = static_cast<T *>(a.psi[c][1]);
+                if (R.psi[c][1]) {
+                    T *ps = static_cast<T *>(R.psi[c][1]);
                     const double psi = a.pml_b[a2][coord[a2]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a2][coord[a2]] * t2;
                     __builtin_nontemporal_store((T)psi, ps + t);
                     t2 += psi;
@@ -230,15 +268,15 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
             const double Eo = (double)Ec[q];
             double En;
             if (KIND == K_BACKGROUND) {
-                En = Eo + a.inv_eps * (a.dt * curl) - srcterm;
-                if (ENERGY && sample) ef += 0.5 / a.inv_eps * Eo * En;
+                En = Eo + R.inv_eps * (a.dt * curl) - srcterm;
+                if (ENERGY && sample) ef += 0.5 / R.inv_eps * Eo * En;
             } else if (KIND == K_DRUDE) {
                 T *Vp = static_cast<T *>(a.Pcur[c]);
                 const double V = (double)__builtin_nontemporal_load(Vp + m);
-                En = Eo + a.inv_eps * (a.dt * curl - V) - srcterm;
+                En = Eo + R.inv_eps * (a.dt * curl - V) - srcterm;
                 __builtin_nontemporal_store((T)(a.coef[0] * En + a.coef[1] * V), Vp + m);
                 if (ENERGY && sample) {
-                    ef += 0.5 / a.inv_eps * Eo * En;
+                    ef += 0.5 / R.inv_eps * Eo * En;
                     const double v = V / a.dt;
                     ep += 0.5 * a.coef[2] * v * v;
                 }
@@ -247,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
                 T *Pn_ = static_cast<T *>(a.Pnew[c]);
                 const double Pc = (double)Pc_[m], Pp = (double)Pn_[m];
-                En = Eo + a.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
+                En = Eo + R.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
                 float4 *hp = static_cast<float4 *>(a.hid[c]) + m;
                 float4 hv = *hp;
                 const float x[7] = {(float)(En * a.cscale[0]), (float)(Pc * a.cscale[1]),
@@ -264,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - force * cf[5];
                 Pn_[m] = (T)Pnew;
                 if (ENERGY && sample) {
-                    ef += 0.5 / a.inv_eps * Eo * En;
+                    ef += 0.5 / R.inv_eps * Eo * En;
                     const double rho = cf[3] / sig;
                     const double v = (Pc - Pp) / a.dt;
                     ep += 0.5 * rho * (v * v + cf[4] * Pc * Pp);
@@ -273,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
                 T *Pn_ = static_cast<T *>(a.Pnew[c]);
                 const double Pc = (double)Pc_[m], Pp = (double)Pn_[m];
-                En = Eo + a.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
+                En = Eo + R.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
                 const double *cf = a.coef;
                 double S = 0.0;
                 V4 yc[NG > 0 ? NG : 1], yp[NG > 0 ? NG : 1];
@@ -303,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                     Yn[(long long)g * a.mcells + m] = o;
                 }
                 if (ENERGY && sample) {
-                    ef += 0.5 / a.inv_eps * Eo * En;
+                    ef += 0.5 / R.inv_eps * Eo * En;
                     const double rho = cf[3] / sig;
                     const double v = (Pc - Pp) / a.dt;
                     ep += 0.5 * rho * (v * v + cf[4] * Pc * Pp);
@@ -462,10 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, bool PML>
 __global__ __launch_bounds__(kBlock) void k_update_h(const HArgs a) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (t >= a.ext[0] * a.ext12) return;
+    RegV R;
+    const int t = pick_region(a, 1.0, xcd_block(blockIdx.x, gridDim.x), R) * kBlock + threadIdx.x;
+    if (t >= R.ext[0] * R.ext12) return;
     int i, j, k;
-    unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
+    unflatten<DIM>(t, R.lo, R.ext, R.ext12, i, j, k);
     const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
     const int q = i * s0 + j * s1 + k;
     const int coord[3] = {i, j, k};
@@ -480,14 +519,14 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const HArgs a) {
         if (axis_live(DIM, a2) && e_active(DIM, a1))
             t2 = at_plus<T>(a.E[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]) - ldd<T>(a.E[a1], q);
         if (PML) {
-            if (a.psi[c][0]) {
-                T *ps = static_cast<T *>(a.psi[c][0]);
+            if (R.psi[c][0]) {
+                T *ps = static_cast<T *>(R.psi[c][0]);
                 const double psi = a.pml_b[a1][coord[a1]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a1][coord[a1]] * t1;
                 __builtin_nontemporal_store((T)psi, ps + t);
                 t1 += psi;
             }
-            if (a.psi[c][1]) {
-                T *ps = static_cast<T *>(a.psi[c][1]);
+            if (R.psi[c][1]) {
+                T *ps = static_cast<T *>(R.psi[c][1]);
                 const double psi = a.pml_b[a2][coord[a2]] * (double)__builtin_nontemporal_load(ps + t) + a.pml_c[a2][coord[a2]] * t2;
                 __builtin_nontemporal_store((T)psi, ps + t);
                 t2 += psi;

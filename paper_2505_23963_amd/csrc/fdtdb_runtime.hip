@@ -90,6 +90,15 @@ struct Region {
     long long cells() const { return (long long)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
 };
 
+// one kernel launch of a step: a single region, or a group of background regions (grouped
+// launches replace many small launches whose cost is mostly launch latency)
+struct Launch {
+    std::vector<int> regs;
+    bool grouped = false, pml = false, energy = false;
+    long long blocks = 0, cells = 0, block_base = 0;
+    RegionDesc *rd = nullptr;
+};
+
 struct Pending {
     int rec;
     hipEvent_t a, b;
@@ -153,6 +162,7 @@ struct fdtdb_grid_s {
     std::vector<Probe> probes;
     std::vector<Region> regions;    // E / material update regions
     std::vector<Region> hregions;   // H update regions (CPML partition only)
+    std::vector<Launch> elaunch, hlaunch;
     double *pml_b[3] = {}, *pml_c[3] = {}, *pml_bh[3] = {}, *pml_ch[3] = {};
     Clock *clock = nullptr;
     SourceDev *src_dev = nullptr;
@@ -438,34 +448,94 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     }
     TRY(g->alloc((void **)&g->src_dev, sizeof(SourceDev) * std::max<size_t>(1, sd.size())));
     if (!sd.empty()) HIP_TRY(hipMemcpy(g->src_dev, sd.data(), sizeof(SourceDev) * sd.size(), hipMemcpyHostToDevice));
-    // energy monitors: mark regions, assign partial slots
-    long long base = 0;
-    for (auto &r : g->regions) {
-        r.block_base = base;
-        base += (r.cells() + kBlock - 1) / kBlock;
+    // launches: material regions alone; background E regions grouped; H regions grouped except
+    // those the vectorized 3D kernel takes
+    for (auto &r : g->regions)
         for (auto &e : g->ens)
             if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
+    auto blocks_of = [](const Region &r) { return (r.cells() + kBlock - 1) / kBlock; };
+    auto make = [&](std::vector<Launch> &out, const std::vector<Region> &rs, const std::vector<int> &idx, bool group) {
+        for (size_t s = 0; s < idx.size();) {
+            Launch L;
+            const size_t n = group ? std::min<size_t>(kMaxGroup, idx.size() - s) : 1;
+            for (size_t q = 0; q < n; q++) {
+                const Region &rg = rs[idx[s + q]];
+                L.regs.push_back(idx[s + q]);
+                L.pml |= rg.pml_mask != 0;
+                L.energy |= rg.energy;
+                L.blocks += blocks_of(rg);
+                L.cells += rg.cells();
+            }
+            L.grouped = n > 1;
+            out.push_back(L);
+            s += n;
+        }
+    };
+    {
+        std::vector<int> bg, solo;
+        for (int i = 0; i < (int)g->regions.size(); i++) (g->regions[i].mat < 0 ? bg : solo).push_back(i);
+        make(g->elaunch, g->regions, bg, bg.size() > 1);
+        make(g->elaunch, g->regions, solo, false);
+        std::vector<int> hg, hv;
+        for (int i = 0; i < (int)g->hregions.size(); i++) {
+            const Region &rg = g->hregions[i];
+            const bool v4 = g->ndim == 3 && !rg.pml_mask && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 &&
+                            g->n[2] % 4 == 0;
+            (v4 ? hv : hg).push_back(i);
+        }
+        make(g->hlaunch, g->hregions, hg, hg.size() > 1);
+        make(g->hlaunch, g->hregions, hv, false);
+    }
+    long long base = 0;
+    for (auto &L : g->elaunch) {
+        L.block_base = base;
+        base += L.blocks;
     }
     g->total_blocks = base;
+    for (int ph = 0; ph < 2; ph++)
+        for (auto &L : ph ? g->hlaunch : g->elaunch) {
+            if (!L.grouped) continue;
+            const std::vector<Region> &rs = ph ? g->hregions : g->regions;
+            std::vector<RegionDesc> d(L.regs.size());
+            int b0 = 0;
+            for (size_t q = 0; q < L.regs.size(); q++) {
+                const Region &rg = rs[L.regs[q]];
+                RegionDesc &x = d[q];
+                for (int a = 0; a < 3; a++) { x.lo[a] = rg.lo[a]; x.ext[a] = rg.hi[a] - rg.lo[a]; }
+                x.ext12 = x.ext[1] * x.ext[2];
+                x.block0 = b0;
+                b0 += (int)blocks_of(rg);
+                x.inv_eps = 1.0 / rg.eps;
+                for (int c = 0; c < 3; c++)
+                    for (int t = 0; t < 2; t++) x.psi[c][t] = ph ? rg.psiH[c][t] : rg.psiE[c][t];
+            }
+            TRY(g->alloc((void **)&L.rd, sizeof(RegionDesc) * d.size()));
+            HIP_TRY(hipMemcpy(L.rd, d.data(), sizeof(RegionDesc) * d.size(), hipMemcpyHostToDevice));
+        }
     for (auto &e : g->ens) {
         e.nslots = base;
         TRY(g->alloc((void **)&e.partial, 24 * (size_t)base));
     }
-    g->launches_per_step = 1 + (int)g->regions.size() + (int)g->hregions.size() + (int)g->ens.size() + (int)g->dfts.size();
+    g->launches_per_step = 1 + (int)g->elaunch.size() + (int)g->hlaunch.size() + (int)g->ens.size() + (int)g->dfts.size();
     for (int ph = 0; ph < 2; ph++) {
+        const std::vector<Launch> &ls = ph ? g->hlaunch : g->elaunch;
         const std::vector<Region> &rs = ph ? g->hregions : g->regions;
-        for (size_t ri = 0; ri < rs.size(); ri++) {
-            const Region &r = rs[ri];
-            double be, bh;
-            region_bytes(g, r, &be, &bh);
+        for (size_t li = 0; li < ls.size(); li++) {
+            const Launch &L = ls[li];
+            const Region &r0 = rs[L.regs[0]];
             fdtdb_kernel_record k{};
-            k.region = (int)ri;
+            k.region = (int)li;
             k.phase = ph;
-            k.kind = ph == 0 && r.mat >= 0 ? g->mats[r.mat].kind : K_BACKGROUND;
-            k.n_bath = ph == 0 && r.mat >= 0 ? g->mats[r.mat].nb : 0;
-            k.pml = r.pml_mask != 0;
-            k.cells = r.cells();
-            k.bytes = (ph == 0 ? be : bh) * (double)r.cells();
+            k.kind = ph == 0 && r0.mat >= 0 ? g->mats[r0.mat].kind : K_BACKGROUND;
+            k.n_bath = ph == 0 && r0.mat >= 0 ? g->mats[r0.mat].nb : 0;
+            k.pml = L.pml;
+            k.cells = L.cells;
+            k.bytes = 0.0;
+            for (int ri : L.regs) {
+                double be, bh;
+                region_bytes(g, rs[ri], &be, &bh);
+                k.bytes += (ph == 0 ? be : bh) * (double)rs[ri].cells();
+            }
             g->records.push_back(k);
         }
     }
@@ -537,7 +607,8 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     const long long n = g->steps;
     const int cur = (int)(n & 1), nxt = cur ^ 1;
     HIP_TRY(launch_tick(g->clock, g->src_dev, (int)g->srcs.size(), g->dt, g->stream));
-    for (auto &r : g->regions) {
+    for (auto &L : g->elaunch) {
+        const Region &r = g->regions[L.regs[0]];
         EArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
         fill_fields(g, a.n, a.per);
@@ -545,6 +616,13 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         a.ext12 = a.ext[1] * a.ext[2];
         a.dt = g->dt;
         a.inv_eps = 1.0 / r.eps;
+        if (L.grouped) {
+            for (int ax = 0; ax < 3; ax++) { a.lo[ax] = 0; a.ext[ax] = 1; }
+            a.ext[0] = (int)(L.blocks * kBlock);
+            a.ext12 = 1;
+            a.rd = L.rd;
+            a.nrd = (int)L.regs.size();
+        }
         int kind = K_BACKGROUND, ng = 0;
         for (int c = 0; c < 3; c++)
             for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiE[c][t];
@@ -583,7 +661,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             d.profile = S.profile_dev;
         }
         a.nen = 0;
-        if (r.energy) {
+        if (L.energy) {
             for (auto &e : g->ens) {
                 EnergyDev &d = a.en[a.nen++];
                 for (int ax = 0; ax < 3; ax++) { d.lo[ax] = (int)e.lo[ax]; d.hi[ax] = (int)e.hi[ax]; }
@@ -591,8 +669,8 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
                 d.partial = e.partial;
             }
         }
-        a.block_base = r.block_base;
-        const int rec = (int)(&r - &g->regions[0]);
+        a.block_base = L.block_base;
+        const int rec = (int)(&L - &g->elaunch[0]);
         Pending pe{rec, nullptr, nullptr};
         if (g->profiling) {
             pe.a = take_event(g);
@@ -601,7 +679,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             HIP_TRY(hipEventRecord(pe.a, g->stream));
         }
         const double *ch = r.mat >= 0 && !g->mats[r.mat].coef.empty() ? g->mats[r.mat].coef.data() : nullptr;
-        HIP_TRY(launch_update_e(g->ndim, g->f64, a, ch, kind, ng, r.pml_mask != 0, r.energy, g->stream));
+        HIP_TRY(launch_update_e(g->ndim, g->f64, a, ch, kind, ng, L.pml, L.energy, g->stream));
         if (g->profiling) {
             HIP_TRY(hipEventRecord(pe.b, g->stream));
             g->pending.push_back(pe);
@@ -612,7 +690,8 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     for (auto &pr : g->probes)
         HIP_TRY(launch_probe(g->f64, g->E[pr.comp], g->mats[pr.mat].P[nxt][pr.comp], pr.q, pr.m, pr.n, g->clock,
                              pr.capacity, pr.E, pr.P, g->stream));
-    for (auto &r : g->hregions) {
+    for (auto &L : g->hlaunch) {
+        const Region &r = g->hregions[L.regs[0]];
         HArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
         fill_fields(g, a.n, a.per);
@@ -622,7 +701,14 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         for (int c = 0; c < 3; c++)
             for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiH[c][t];
         for (int ax = 0; ax < 3; ax++) { a.pml_b[ax] = g->pml_bh[ax]; a.pml_c[ax] = g->pml_ch[ax]; }
-        const int rec = (int)g->regions.size() + (int)(&r - &g->hregions[0]);
+        if (L.grouped) {
+            for (int ax = 0; ax < 3; ax++) { a.lo[ax] = 0; a.ext[ax] = 1; }
+            a.ext[0] = (int)(L.blocks * kBlock);
+            a.ext12 = 1;
+            a.rd = L.rd;
+            a.nrd = (int)L.regs.size();
+        }
+        const int rec = (int)g->elaunch.size() + (int)(&L - &g->hlaunch[0]);
         Pending pe{rec, nullptr, nullptr};
         if (g->profiling) {
             pe.a = take_event(g);
@@ -630,7 +716,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
             HIP_TRY(hipEventRecord(pe.a, g->stream));
         }
-        HIP_TRY(launch_update_h(g->ndim, g->f64, a, r.pml_mask != 0, g->stream));
+        HIP_TRY(launch_update_h(g->ndim, g->f64, a, L.pml, g->stream));
         if (g->profiling) {
             HIP_TRY(hipEventRecord(pe.b, g->stream));
             g->pending.push_back(pe);

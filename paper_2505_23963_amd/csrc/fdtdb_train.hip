@@ -361,6 +361,7 @@ __global__ __launch_bounds__(TB) void k_adam(double *w64, float *w32, double *m,
     const int e = blockIdx.x * TB + threadIdx.x;
     if (e >= NP) return;
     const double g = grad[e];
+    if (!(g - g == 0.0)) return;      // a non-finite gradient leaves the parameter alone
     const double mn = 0.9 * m[e] + 0.1 * g;
     const double vn = 0.999 * v[e] + 0.001 * g * g;
     m[e] = mn;
@@ -381,6 +382,11 @@ __global__ __launch_bounds__(TB) void k_embed(double *w64, float *w32, double ep
     const double wn = w64[e] * f;
     w64[e] = wn;
     w32[e] = (float)wn;
+}
+
+__global__ __launch_bounds__(TB) void k_to_f32(const double *w64, float *w32) {
+    const int e = blockIdx.x * TB + threadIdx.x;
+    if (e < NP) w32[e] = (float)w64[e];
 }
 
 __global__ void k_fill4(float4 *p, long long n) {
@@ -448,6 +454,7 @@ struct fdtdb_trainer_s {
     double *lossp = nullptr, *partial = nullptr, *grad = nullptr, *lsum = nullptr;
     int wg_blocks = 0, wg_tiles = 0;
     double *w64 = nullptr, *m = nullptr, *v = nullptr;
+    double *snap = nullptr;                 // weights, m, v before the current epoch
     float *w32 = nullptr;
     long long adam_t = 0;
     bool loaded = false, have_w = false;
@@ -552,6 +559,7 @@ fdtdb_status fdtdb_trainer_create(const fdtdb_trainer_desc *d, fdtdb_trainer *ou
     A((void **)&t->m, 8 * (size_t)NP);
     A((void **)&t->v, 8 * (size_t)NP);
     A((void **)&t->w32, 4 * (size_t)NP);
+    A((void **)&t->snap, 48 * (size_t)NP);
     if (st != FDTDB_OK) { fdtdb_trainer_destroy(t); return st; }
     hipError_t e = hipMemcpy(t->coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { fdtdb_trainer_destroy(t); return tfail(FDTDB_E_DEVICE, "hipMemcpy: %s", hipGetErrorString(e)); }
@@ -672,8 +680,20 @@ fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double 
     if (!t || epochs < 0 || !(lr > 0.0) || !(lr_decay > 0.0)) return tfail(FDTDB_E_INVALID, "bad argument");
     if (!t->loaded || !t->have_w) return tfail(FDTDB_E_STATE, "load data and set weights first");
     const long long nwin = t->T / t->W;
-    double rate = lr;
-    for (int ep = 0; ep < epochs; ep++) {
+    double rate = lr, best = HUGE_VAL;
+    int retries = 0;
+    // two snapshots of weights and Adam state: the start of the current epoch and of the one before
+    // (the weights an epoch ends with are only judged by the next epoch's loss)
+    long long t_snap[2] = {t->adam_t, t->adam_t};
+    double rate_snap[2] = {rate, rate};
+    int cur = 0;
+    for (int ep = 0; ep < epochs;) {
+        double *sn = t->snap + 3 * (size_t)NP * cur;
+        THIP(hipMemcpyAsync(sn, t->w64, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+        THIP(hipMemcpyAsync(sn + NP, t->m, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+        THIP(hipMemcpyAsync(sn + 2 * NP, t->v, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+        t_snap[cur] = t->adam_t;
+        rate_snap[cur] = rate;
         hipLaunchKernelGGL(k_fill4, dim3(nblk(t->N)), dim3(TB), 0, t->stream, t->h, t->N);
         THIP(hipGetLastError());
         TTRY(zero(t, t->lsum, 1));
@@ -685,10 +705,31 @@ fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double 
                                c1, c2);
             THIP(hipGetLastError());
         }
-        if (loss_per_epoch) {
-            THIP(hipMemcpyAsync(&loss_per_epoch[ep], t->lsum, 8, hipMemcpyDeviceToHost, t->stream));
+        double L = 0.0;
+        THIP(hipMemcpyAsync(&L, t->lsum, 8, hipMemcpyDeviceToHost, t->stream));
+        THIP(hipStreamSynchronize(t->stream));
+        if (!std::isfinite(L) || L > 100.0 * best) {
+            // the recurrence ran away: go back to the start of the previous epoch (the first epoch
+            // goes back to its own start), halve the rate, and repeat from there
+            if (++retries > 12) return tfail(FDTDB_E_DIVERGED, "training diverged (epoch %d)", ep);
+            const int back = ep > 0 ? cur ^ 1 : cur;
+            const double *sb = t->snap + 3 * (size_t)NP * back;
+            THIP(hipMemcpyAsync(t->w64, sb, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+            THIP(hipMemcpyAsync(t->m, sb + NP, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+            THIP(hipMemcpyAsync(t->v, sb + 2 * NP, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
+            hipLaunchKernelGGL(k_to_f32, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32);
+            THIP(hipGetLastError());
+            t->adam_t = t_snap[back];
+            rate = 0.5 * rate_snap[back];
+            if (ep > 0) ep--;
+            cur = back;
+            continue;
         }
+        best = std::min(best, L);
+        if (loss_per_epoch) loss_per_epoch[ep] = L;
         rate *= lr_decay;
+        cur ^= 1;
+        ep++;
     }
     THIP(hipStreamSynchronize(t->stream));
     return FDTDB_OK;
