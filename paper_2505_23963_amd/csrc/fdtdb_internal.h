@@ -82,6 +82,12 @@ struct RegionDesc {
     void *psi[3][2];
 };
 constexpr int kMaxGroup = 32;
+// region table of a grouped launch: first blocks (unused entries hold INT_MAX, so every entry can
+// be read unconditionally), then the regions
+struct RegionTable {
+    int block0[kMaxGroup];
+    RegionDesc d[kMaxGroup];
+};
 
 struct EArgs {
     void *E[3];
@@ -113,7 +119,7 @@ struct EArgs {
     int nen;
     EnergyDev en[kMaxEnergy];
     long long block_base;            // first partial slot of this launch
-    const RegionDesc *rd;            // grouped launch: region table (nrd > 0), else the box above
+    const RegionTable *rd;           // grouped launch: region table (nrd > 0), else the box above
     int nrd;
 };
 
@@ -127,7 +133,7 @@ struct HArgs {
     double dt;
     void *psi[3][2];
     const double *pml_b[3], *pml_c[3];
-    const RegionDesc *rd;            // grouped launch: region table (nrd > 0)
+    const RegionTable *rd;           // grouped launch: region table (nrd > 0)
     int nrd;
 };
 

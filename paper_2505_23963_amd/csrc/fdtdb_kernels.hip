@@ -159,10 +159,10 @@ struct RegV {
 template <class A>
 __device__ __forceinline__ int pick_region(const A &a, double inv_eps, int b, RegV &R) {
     if (a.nrd > 0) {
-        int r = 0;
-        for (int s = 1; s < kMaxGroup; ++s)
-            if (s < a.nrd && b >= a.rd[s].block0) r = s;
-        const RegionDesc &D = a.rd[r];
+        int r = -1;
+#pragma unroll
+        for (int s = 0; s < kMaxGroup; ++s) r += b >= a.rd->block0[s];
+        const RegionDesc &D = a.rd->d[r];
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
             R.lo[x] = D.lo[x];
@@ -172,7 +172,7 @@ __device__ __forceinline__ int pick_region(const A &a, double inv_eps, int b, Re
         }
         R.ext12 = D.ext12;
         R.inv_eps = D.inv_eps;
-        return b - D.block0;
+        return b - a.rd->block0[r];
     }
 #pragma unroll
     for (int x = 0; x < 3; ++x) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -96,7 +97,7 @@ struct Launch {
     std::vector<int> regs;
     bool grouped = false, pml = false, energy = false;
     long long blocks = 0, cells = 0, block_base = 0;
-    RegionDesc *rd = nullptr;
+    RegionTable *rd = nullptr;
 };
 
 struct Pending {
@@ -177,7 +178,7 @@ struct fdtdb_grid_s {
     int launches_per_step = 0;
     std::vector<void *> allocs;
     // profiling
-    bool profiling = false;
+    int profiling = 0;             // 0 off, 1 every E/H launch, 2 dispersive-material E launches only
     std::vector<fdtdb_kernel_record> records;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
@@ -496,21 +497,23 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         for (auto &L : ph ? g->hlaunch : g->elaunch) {
             if (!L.grouped) continue;
             const std::vector<Region> &rs = ph ? g->hregions : g->regions;
-            std::vector<RegionDesc> d(L.regs.size());
+            RegionTable tab{};
+            for (int s = 0; s < kMaxGroup; s++) tab.block0[s] = INT_MAX;
             int b0 = 0;
             for (size_t q = 0; q < L.regs.size(); q++) {
                 const Region &rg = rs[L.regs[q]];
-                RegionDesc &x = d[q];
+                RegionDesc &x = tab.d[q];
                 for (int a = 0; a < 3; a++) { x.lo[a] = rg.lo[a]; x.ext[a] = rg.hi[a] - rg.lo[a]; }
                 x.ext12 = x.ext[1] * x.ext[2];
                 x.block0 = b0;
+                tab.block0[q] = b0;
                 b0 += (int)blocks_of(rg);
                 x.inv_eps = 1.0 / rg.eps;
                 for (int c = 0; c < 3; c++)
                     for (int t = 0; t < 2; t++) x.psi[c][t] = ph ? rg.psiH[c][t] : rg.psiE[c][t];
             }
-            TRY(g->alloc((void **)&L.rd, sizeof(RegionDesc) * d.size()));
-            HIP_TRY(hipMemcpy(L.rd, d.data(), sizeof(RegionDesc) * d.size(), hipMemcpyHostToDevice));
+            TRY(g->alloc((void **)&L.rd, sizeof(RegionTable)));
+            HIP_TRY(hipMemcpy(L.rd, &tab, sizeof(RegionTable), hipMemcpyHostToDevice));
         }
     for (auto &e : g->ens) {
         e.nslots = base;
@@ -672,7 +675,8 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         a.block_base = L.block_base;
         const int rec = (int)(&L - &g->elaunch[0]);
         Pending pe{rec, nullptr, nullptr};
-        if (g->profiling) {
+        const bool ev = g->profiling == 1 || (g->profiling == 2 && kind != K_BACKGROUND);
+        if (ev) {
             pe.a = take_event(g);
             pe.b = take_event(g);
             if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
@@ -680,7 +684,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         }
         const double *ch = r.mat >= 0 && !g->mats[r.mat].coef.empty() ? g->mats[r.mat].coef.data() : nullptr;
         HIP_TRY(launch_update_e(g->ndim, g->f64, a, ch, kind, ng, L.pml, L.energy, g->stream));
-        if (g->profiling) {
+        if (ev) {
             HIP_TRY(hipEventRecord(pe.b, g->stream));
             g->pending.push_back(pe);
         }
@@ -710,14 +714,14 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         }
         const int rec = (int)g->elaunch.size() + (int)(&L - &g->hlaunch[0]);
         Pending pe{rec, nullptr, nullptr};
-        if (g->profiling) {
+        if (g->profiling == 1) {
             pe.a = take_event(g);
             pe.b = take_event(g);
             if (!pe.a || !pe.b) return fail(FDTDB_E_DEVICE, "event creation failed");
             HIP_TRY(hipEventRecord(pe.a, g->stream));
         }
         HIP_TRY(launch_update_h(g->ndim, g->f64, a, L.pml, g->stream));
-        if (g->profiling) {
+        if (g->profiling == 1) {
             HIP_TRY(hipEventRecord(pe.b, g->stream));
             g->pending.push_back(pe);
         }
@@ -1348,7 +1352,8 @@ fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out) {
 
 fdtdb_status fdtdb_set_profiling(fdtdb_grid g, int on) {
     if (!g) return fail(FDTDB_E_INVALID, "null grid");
-    g->profiling = on != 0;
+    if (on < 0 || on > 2) return fail(FDTDB_E_INVALID, "profiling mode must be 0, 1 or 2");
+    g->profiling = on;
     return FDTDB_OK;
 }
 

@@ -325,8 +325,9 @@ class Grid:
         _check(lib().fdtdb_energy(self.h, mid, _ptr(out), n.value, C.byref(n)))
         return out[:3 * n.value].reshape(-1, 3)
 
-    def set_profiling(self, on: bool):
-        _check(lib().fdtdb_set_profiling(self.h, 1 if on else 0))
+    def set_profiling(self, on, dispersive_only: bool = False):
+        """Events around every E/H launch (on), or only around dispersive-material E launches."""
+        _check(lib().fdtdb_set_profiling(self.h, 0 if not on else (2 if dispersive_only else 1)))
 
     def kernel_records(self):
         n = C.c_int()
