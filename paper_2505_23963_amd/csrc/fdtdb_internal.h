@@ -32,6 +32,30 @@ __device__ __forceinline__ float tanh_f(float a) {
     return 1.0f - 2.0f / (1.0f + __expf(2.0f * a));
 }
 
+// tanh of N values with one branch per wave: when every lane's values lie within |a| < 1/16 the
+// series is used for all of them, otherwise the exponential form (same values as tanh_f).
+template <int N>
+__device__ __forceinline__ void tanh_n(float *v) {
+    float mx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) mx = fmaxf(mx, fabsf(v[i]));
+    if (__all(mx < 0.0625f)) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const float a2 = v[i] * v[i];
+            v[i] = v[i] * (1.0f + a2 * (-1.0f / 3.0f + a2 * (2.0f / 15.0f)));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {     // both forms, selected per value (no branch per value)
+            const float a = v[i], a2 = a * a;
+            const float small = a * (1.0f + a2 * (-1.0f / 3.0f + a2 * (2.0f / 15.0f)));
+            const float big = 1.0f - 2.0f / (1.0f + __expf(2.0f * a));
+            v[i] = fabsf(a) < 0.0625f ? small : big;
+        }
+    }
+}
+
 // Curl axes of component c: (curl F)_c = d_{a1} F_{a2} - d_{a2} F_{a1}.
 __host__ __device__ constexpr int curl_a1(int c) { return c == 0 ? 1 : (c == 1 ? 2 : 0); }
 __host__ __device__ constexpr int curl_a2(int c) { return c == 0 ? 2 : (c == 1 ? 0 : 1); }

@@ -64,40 +64,6 @@ __device__ __forceinline__ double at_plus(const void *f, int q, int coord, int s
 
 typedef const __attribute__((address_space(4))) float *cfptr;
 
-// The closure network on one input vector; weights are uniform over the launch and read through
-// the constant address space (scalar loads).  The empty asm statements keep the compiler from
-// hoisting every weight load to the top (which overflows the scalar register file): each unit's
-// row is loaded right before it is used.
-__device__ __forceinline__ void closure_mlp(cfptr w, const float *x, float *o) {
-    constexpr int W = kClosureWidth;
-    const cfptr W1 = w, b1 = W1 + W * 7, W2 = b1 + W, b2 = W2 + W * W, W3 = b2 + W, b3 = W3 + 5 * W;
-    float z1[W], z2[W];
-#pragma unroll
-    for (int u = 0; u < W; ++u) {
-        float s = b1[u];
-#pragma unroll
-        for (int v = 0; v < 7; ++v) s = fmaf(W1[u * 7 + v], x[v], s);
-        z1[u] = tanh_f(s);
-        if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
-    }
-#pragma unroll
-    for (int u = 0; u < W; ++u) {
-        float s = b2[u];
-#pragma unroll
-        for (int v = 0; v < W; ++v) s = fmaf(W2[u * W + v], z1[v], s);
-        z2[u] = tanh_f(s);
-        __asm__ volatile("" ::: "memory");
-    }
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-        float s = b3[u];
-#pragma unroll
-        for (int v = 0; v < W; ++v) s = fmaf(W3[u * W + v], z2[v], s);
-        o[u] = s;
-        __asm__ volatile("" ::: "memory");
-    }
-}
-
 // soft-current term dt J(t_n) profile / eps of component c at cell (i, j, k)
 __device__ __forceinline__ double source_term(const EArgs &a, const double *amp, int c, int i, int j, int k) {
     double s = 0.0;
@@ -212,6 +178,164 @@ __device__ __forceinline__ void unflatten(int t, const int *lo, const int *ext, 
 // E / material update, generic form: background (vacuum, dielectric, CPML), Drude, and the
 // Lorentz-Bath path for baths too large for the load-first kernel.
 // ---------------------------------------------------------------------------------------------
+// E / polarization update of a Lorentz-Bath material whose bath force comes from the learned
+// closure.  Per E component and cell: x = [E s_E, P s_P, V s_V, h] -> tanh(W1 x + b1) ->
+// tanh(W2 z1 + b2) -> o = W3 z2 + b3; h += o[0:4]; the bath force term of eq:Pz_update-LB is
+// o[4] / s_S.  Layers 1 and 3 run on the vector ALU with the weights read through the constant
+// address space; layer 2 (32 x 32, three quarters of the work) runs on the matrix cores as FP32
+// MFMA 16x16x4 over tiles of 16 cells: each wave stages its 64 cells' z1 rows in LDS, reads them
+// back in the B-operand layout (lane l: cell l mod 16 of the tile, feature 4 s + l / 16 at step s),
+// holds W2 as the A operand in registers, and writes z2 back over the tile's rows, from where each
+// lane reads its own cell's row for layer 3.  Every lane of a wave takes part (lanes past the end
+// of the region compute on a clamped cell and store nothing).
+// ---------------------------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kClRow = 36;    // LDS row stride (floats): 16 rows x 4 groups of B reads hit 64 banks once
+
+template <int DIM, typename T, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
+    __shared__ float lds[kBlock / 64][64 * kClRow];
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, jl = lane & 15;
+    float *row = lds[tid >> 6];
+    const int t0 = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
+    const int ncell = a.ext[0] * a.ext12;
+    const bool live = t0 < ncell;
+    const int t = live ? t0 : ncell - 1;
+    constexpr int W = kClosureWidth;
+    const cfptr w = (cfptr)a.cw;
+    const cfptr W1 = w, b1 = W1 + W * 7, W3 = b1 + W + W * W + W, b3 = W3 + 5 * W;
+    // layer-2 operands of this lane: A = W2 rows 16 h + (lane mod 16), columns 4 s + lane / 16;
+    // accumulator start = b2 of units 16 h + 4 (lane / 16) + v
+    const float *W2 = a.cw + W * 7 + W;
+    const float *b2 = W2 + W * W;
+    float wa[2][8];
+    f4v bias2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) wa[h][s] = W2[(16 * h + jl) * W + 4 * s + g];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bias2[h][v] = b2[16 * h + 4 * g + v];
+    }
+    double ef = 0.0, ep = 0.0;
+    bool sample = false;
+    if (ENERGY) {
+        const long long st = a.clock->step;
+        for (int e = 0; e < a.nen; ++e) sample |= (st % a.en[e].every) == 0;
+    }
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    int i, j, k;
+    unflatten<DIM>(t, a.lo, a.ext, a.ext12, i, j, k);
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const int coord[3] = {i, j, k};
+    const int stride[3] = {s0, s1, 1};
+    const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+    const double sig = a.sigma ? ldd<T>(a.sigma, m) : a.sigma0;
+    const double *cf = a.coef;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (!e_active(DIM, c)) continue;
+        const int a1 = curl_a1(c), a2 = curl_a2(c);
+        double t1 = 0.0, t2 = 0.0;
+        if (axis_live(DIM, a1) && h_active(DIM, a2))
+            t1 = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+        if (axis_live(DIM, a2) && h_active(DIM, a1))
+            t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+        const double curl = t1 - t2;
+        const double srcterm = source_term(a, amp, c, i, j, k);
+        T *Ec = static_cast<T *>(a.E[c]);
+        T *Pc_ = static_cast<T *>(a.Pcur[c]);
+        T *Pn_ = static_cast<T *>(a.Pnew[c]);
+        const double Eo = (double)Ec[q];
+        const double Pc = (double)Pc_[m], Pp = (double)Pn_[m];
+        const double En = Eo + a.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
+        float4 *hp = static_cast<float4 *>(a.hid[c]) + m;
+        float4 hv = *hp;
+        const float x[7] = {(float)(En * a.cscale[0]), (float)(Pc * a.cscale[1]),
+                            (float)((Pc - Pp) / a.dt * a.cscale[2]), hv.x, hv.y, hv.z, hv.w};
+        // layer 1 (vector ALU), z1 row to LDS
+        float z1[W];
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            float s = b1[u];
+#pragma unroll
+            for (int v = 0; v < 7; ++v) s = fmaf(W1[u * 7 + v], x[v], s);
+            z1[u] = s;
+            if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
+        }
+        tanh_n<W>(z1);
+#pragma unroll
+        for (int u = 0; u < W; u += 4)
+            *reinterpret_cast<float4 *>(row + lane * kClRow + u) = make_float4(z1[u], z1[u + 1], z1[u + 2], z1[u + 3]);
+        __syncthreads();
+        // layer 2 (matrix cores), tile by tile; z2 overwrites the tile's rows
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            f4v acc0 = bias2[0], acc1 = bias2[1];
+            const float *src = row + (16 * r + jl) * kClRow + g;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const float bv = src[4 * s];
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[0][s], bv, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[1][s], bv, acc1, 0, 0, 0);
+            }
+            float zz[8] = {acc0[0], acc0[1], acc0[2], acc0[3], acc1[0], acc1[1], acc1[2], acc1[3]};
+            tanh_n<8>(zz);
+            float *dst = row + (16 * r + jl) * kClRow + 4 * g;
+            *reinterpret_cast<float4 *>(dst) = make_float4(zz[0], zz[1], zz[2], zz[3]);
+            *reinterpret_cast<float4 *>(dst + 16) = make_float4(zz[4], zz[5], zz[6], zz[7]);
+        }
+        __syncthreads();
+        // layer 3 (vector ALU) on this lane's own row
+        float z2[W];
+#pragma unroll
+        for (int u = 0; u < W; u += 4) {
+            const float4 v4 = *reinterpret_cast<const float4 *>(row + lane * kClRow + u);
+            z2[u] = v4.x; z2[u + 1] = v4.y; z2[u + 2] = v4.z; z2[u + 3] = v4.w;
+        }
+        __syncthreads();
+        float o[5];
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            float s = b3[u];
+#pragma unroll
+            for (int v = 0; v < W; ++v) s = fmaf(W3[u * W + v], z2[v], s);
+            o[u] = s;
+            __asm__ volatile("" ::: "memory");
+        }
+        const double force = (double)o[4] * a.cscale[3];
+        const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - force * cf[5];
+        if (live) {
+            hv.x += o[0];
+            hv.y += o[1];
+            hv.z += o[2];
+            hv.w += o[3];
+            *hp = hv;
+            Ec[q] = (T)En;
+            Pn_[m] = (T)Pnew;
+        }
+        if (ENERGY && sample) {
+            ef += 0.5 / a.inv_eps * Eo * En;
+            const double rho = cf[3] / sig;
+            const double vv = (Pc - Pp) / a.dt;
+            ep += 0.5 * rho * (vv * vv + cf[4] * Pc * Pp);
+        }
+    }
+    if (ENERGY && sample) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (h_active(DIM, c)) {
+                const double h = ldd<T>(a.H[c], q);
+                ef += 0.5 * h * h;
+            }
+        energy_partials(a, live, i, j, k, ef, ep, 0.0);
+    }
+}
+
+
+// ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, int KIND, int NG, bool PML, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     using V4 = vec4_t<T>;
@@ -279,33 +403,6 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                     ef += 0.5 / R.inv_eps * Eo * En;
                     const double v = V / a.dt;
                     ep += 0.5 * a.coef[2] * v * v;
-                }
-            } else if (KIND == K_CLOSURE) {
-                // Lorentz polarization with the bath force produced by the learned closure
-                T *Pc_ = static_cast<T *>(a.Pcur[c]);
-                T *Pn_ = static_cast<T *>(a.Pnew[c]);
-                const double Pc = (double)Pc_[m], Pp = (double)Pn_[m];
-                En = Eo + R.inv_eps * (a.dt * curl - (Pc - Pp)) - srcterm;
-                float4 *hp = static_cast<float4 *>(a.hid[c]) + m;
-                float4 hv = *hp;
-                const float x[7] = {(float)(En * a.cscale[0]), (float)(Pc * a.cscale[1]),
-                                    (float)((Pc - Pp) / a.dt * a.cscale[2]), hv.x, hv.y, hv.z, hv.w};
-                float o[5];
-                closure_mlp((cfptr)a.cw, x, o);
-                hv.x += o[0];
-                hv.y += o[1];
-                hv.z += o[2];
-                hv.w += o[3];
-                *hp = hv;
-                const double *cf = a.coef;
-                const double force = (double)o[4] * a.cscale[3];
-                const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - force * cf[5];
-                Pn_[m] = (T)Pnew;
-                if (ENERGY && sample) {
-                    ef += 0.5 / R.inv_eps * Eo * En;
-                    const double rho = cf[3] / sig;
-                    const double v = (Pc - Pp) / a.dt;
-                    ep += 0.5 * rho * (v * v + cf[4] * Pc * Pp);
                 }
             } else {  // K_BATH (NG == 0: plain Lorentz)
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
@@ -784,7 +881,15 @@ static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int n
         return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, ch, energy, s)
                    : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, ch, energy, s);
     if (kind == K_DRUDE) return launch_e_pml<DIM, T, K_DRUDE, 0, false>(a, ch, energy, s);
-    if (kind == K_CLOSURE) return launch_e_pml<DIM, T, K_CLOSURE, 0, false>(a, ch, energy, s);
+    if (kind == K_CLOSURE) {
+        const long long n = (long long)a.ext[0] * a.ext12;
+        if (n == 0) return hipSuccess;
+        if (energy)
+            hipLaunchKernelGGL((k_update_e_closure<DIM, T, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_update_e_closure<DIM, T, false>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     if (kind == K_BATH) {
         switch (ng) {
             case 0: return launch_e_pml<DIM, T, K_BATH, 0, false>(a, ch, energy, s);
