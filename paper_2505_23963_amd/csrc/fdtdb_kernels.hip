@@ -644,17 +644,57 @@ __device__ __forceinline__ double lane4(const vec4_t<T> &v, int e) {
     return e == 0 ? (double)v.x : e == 1 ? (double)v.y : e == 2 ? (double)v.z : (double)v.w;
 }
 
+// region of a v4 launch (always from the table) and the first of the thread's 4 z-cells
+struct Cell4 {
+    int i, j, k, tc;       // cell of the first z value, region-local index of that cell
+    bool live;
+};
+template <class A>
+__device__ __forceinline__ const RegionDesc &v4_region(const A &a, Cell4 &c) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int r = -1;
+#pragma unroll
+    for (int s = 0; s < kMaxGroup; ++s) r += b >= a.rd->block0[s];
+    const RegionDesc &D = a.rd->d[r];
+    const int t = (b - a.rd->block0[r]) * kBlock + threadIdx.x;
+    const int ext2q = D.ext[2] >> 2;
+    c.live = t < D.ext[0] * D.ext[1] * ext2q;
+    const int rr = t / ext2q;
+    const int kq = t - rr * ext2q;
+    const int r2 = rr / D.ext[1];
+    c.k = D.lo[2] + 4 * kq;
+    c.i = D.lo[0] + r2;
+    c.j = D.lo[1] + (rr - r2 * D.ext[1]);
+    c.tc = 4 * t;
+    return D;
+}
+
+// CPML convolution of one curl term for 4 z-consecutive cells: psi <- b psi + c dF, dF += psi
+template <typename T>
+__device__ __forceinline__ void cpml4(void *psi, int tc, int ax, int i, int j, int k, const double *pb,
+                                      const double *pc, double *term) {
+    using V = vec4_t<T>;
+    V *pp = reinterpret_cast<V *>(static_cast<T *>(psi) + tc);
+    const V p = *pp;
+    double o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int x = ax == 0 ? i : ax == 1 ? j : k + e;
+        o[e] = pb[x] * lane4<T>(p, e) + pc[x] * term[e];
+        term[e] += o[e];
+    }
+    V w;
+    w.x = (T)o[0]; w.y = (T)o[1]; w.z = (T)o[2]; w.w = (T)o[3];
+    *pp = w;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     using V = vec4_t<T>;
-    const int ext2q = a.ext[2] >> 2;
-    const int total = a.ext[0] * a.ext[1] * ext2q;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (t >= total) return;
-    const int r = t / ext2q;
-    const int k = a.lo[2] + 4 * (t - r * ext2q);
-    const int r2 = r / a.ext[1];
-    const int i = a.lo[0] + r2, j = a.lo[1] + (r - r2 * a.ext[1]);
+    Cell4 C;
+    const RegionDesc &D = v4_region(a, C);
+    if (!C.live) return;
+    const int i = C.i, j = C.j, k = C.k;
     const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
     const int q = i * s0 + j * s1 + k;
     const T *Ex = static_cast<const T *>(a.E[0]);
@@ -679,7 +719,8 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     V *Hz = reinterpret_cast<V *>(static_cast<T *>(a.H[2]) + q);
     const V hx = *Hx, hy = *Hy, hz = *Hz;
     const double dt = a.dt;
-    double ox[4], oy[4], oz[4];
+    // curl terms per component: t1 along axis a1, t2 along axis a2 (Hx: y, z; Hy: z, x; Hz: x, y)
+    double tx1[4], tx2[4], ty1[4], ty2[4], tz1[4], tz2[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const double exe = lane4<T>(ex, e), eye = lane4<T>(ey, e), eze = lane4<T>(ez, e);
@@ -687,18 +728,98 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
         const double eyn = e < 3 ? lane4<T>(ey, e + 1) : ey_z;
         const double ezy = oky ? lane4<T>(ez_y, e) : 0.0, exy = oky ? lane4<T>(ex_y, e) : 0.0;
         const double eyx = okx ? lane4<T>(ey_x, e) : 0.0, ezx = okx ? lane4<T>(ez_x, e) : 0.0;
-        // Hx -= dt (d_y Ez - d_z Ey); Hy -= dt (d_z Ex - d_x Ez); Hz -= dt (d_x Ey - d_y Ex)
-        ox[e] = lane4<T>(hx, e) - dt * ((ezy - eze) - (eyn - eye));
-        oy[e] = lane4<T>(hy, e) - dt * ((exn - exe) - (ezx - eze));
-        oz[e] = lane4<T>(hz, e) - dt * ((eyx - eye) - (exy - exe));
+        tx1[e] = ezy - eze; tx2[e] = eyn - eye;
+        ty1[e] = exn - exe; ty2[e] = ezx - eze;
+        tz1[e] = eyx - eye; tz2[e] = exy - exe;
+    }
+    if (D.psi[0][0]) cpml4<T>(D.psi[0][0], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tx1);
+    if (D.psi[0][1]) cpml4<T>(D.psi[0][1], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], tx2);
+    if (D.psi[1][0]) cpml4<T>(D.psi[1][0], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], ty1);
+    if (D.psi[1][1]) cpml4<T>(D.psi[1][1], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], ty2);
+    if (D.psi[2][0]) cpml4<T>(D.psi[2][0], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], tz1);
+    if (D.psi[2][1]) cpml4<T>(D.psi[2][1], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tz2);
+    V wx, wy, wz;
+    wx.x = (T)(lane4<T>(hx, 0) - dt * (tx1[0] - tx2[0])); wx.y = (T)(lane4<T>(hx, 1) - dt * (tx1[1] - tx2[1]));
+    wx.z = (T)(lane4<T>(hx, 2) - dt * (tx1[2] - tx2[2])); wx.w = (T)(lane4<T>(hx, 3) - dt * (tx1[3] - tx2[3]));
+    wy.x = (T)(lane4<T>(hy, 0) - dt * (ty1[0] - ty2[0])); wy.y = (T)(lane4<T>(hy, 1) - dt * (ty1[1] - ty2[1]));
+    wy.z = (T)(lane4<T>(hy, 2) - dt * (ty1[2] - ty2[2])); wy.w = (T)(lane4<T>(hy, 3) - dt * (ty1[3] - ty2[3]));
+    wz.x = (T)(lane4<T>(hz, 0) - dt * (tz1[0] - tz2[0])); wz.y = (T)(lane4<T>(hz, 1) - dt * (tz1[1] - tz2[1]));
+    wz.z = (T)(lane4<T>(hz, 2) - dt * (tz1[2] - tz2[2])); wz.w = (T)(lane4<T>(hz, 3) - dt * (tz1[3] - tz2[3]));
+    *Hx = wx;
+    *Hy = wy;
+    *Hz = wz;
+}
+
+// ---------------------------------------------------------------------------------------------
+// 3D E update of background regions (vacuum, dielectric, CPML), four z-consecutive cells per
+// thread, regions from the launch's table (no energy sampling: launches with monitors take the
+// generic kernel).
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
+    using V = vec4_t<T>;
+    Cell4 C;
+    const RegionDesc &D = v4_region(a, C);
+    if (!C.live) return;
+    const int i = C.i, j = C.j, k = C.k;
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const T *Hx = static_cast<const T *>(a.H[0]);
+    const T *Hy = static_cast<const T *>(a.H[1]);
+    const T *Hz = static_cast<const T *>(a.H[2]);
+    const bool oky = j > 0 || a.per[1], okx = i > 0 || a.per[0], okz = k > 0 || a.per[2];
+    const int qy = j > 0 ? q - s1 : (a.per[1] ? q + (a.n[1] - 1) * s1 : q);
+    const int qx = i > 0 ? q - s0 : (a.per[0] ? q + (a.n[0] - 1) * s0 : q);
+    const int qz = k > 0 ? q - 1 : (a.per[2] ? q + a.n[2] - 1 : q);
+    const V hx = *reinterpret_cast<const V *>(Hx + q);
+    const V hy = *reinterpret_cast<const V *>(Hy + q);
+    const V hz = *reinterpret_cast<const V *>(Hz + q);
+    const V hz_y = *reinterpret_cast<const V *>(Hz + qy);
+    const V hx_y = *reinterpret_cast<const V *>(Hx + qy);
+    const V hy_x = *reinterpret_cast<const V *>(Hy + qx);
+    const V hz_x = *reinterpret_cast<const V *>(Hz + qx);
+    const double hx_z = okz ? (double)Hx[qz] : 0.0;
+    const double hy_z = okz ? (double)Hy[qz] : 0.0;
+    V *Ex = reinterpret_cast<V *>(static_cast<T *>(a.E[0]) + q);
+    V *Ey = reinterpret_cast<V *>(static_cast<T *>(a.E[1]) + q);
+    V *Ez = reinterpret_cast<V *>(static_cast<T *>(a.E[2]) + q);
+    const V ex = *Ex, ey = *Ey, ez = *Ez;
+    // Ex: t1 = d_y Hz, t2 = d_z Hy;  Ey: t1 = d_z Hx, t2 = d_x Hz;  Ez: t1 = d_x Hy, t2 = d_y Hx
+    double tx1[4], tx2[4], ty1[4], ty2[4], tz1[4], tz2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double hxe = lane4<T>(hx, e), hye = lane4<T>(hy, e), hze = lane4<T>(hz, e);
+        const double hxp = e > 0 ? lane4<T>(hx, e - 1) : hx_z;
+        const double hyp = e > 0 ? lane4<T>(hy, e - 1) : hy_z;
+        const double hzy = oky ? lane4<T>(hz_y, e) : 0.0, hxy = oky ? lane4<T>(hx_y, e) : 0.0;
+        const double hyx = okx ? lane4<T>(hy_x, e) : 0.0, hzx = okx ? lane4<T>(hz_x, e) : 0.0;
+        tx1[e] = hze - hzy; tx2[e] = hye - hyp;
+        ty1[e] = hxe - hxp; ty2[e] = hze - hzx;
+        tz1[e] = hye - hyx; tz2[e] = hxe - hxy;
+    }
+    if (D.psi[0][0]) cpml4<T>(D.psi[0][0], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tx1);
+    if (D.psi[0][1]) cpml4<T>(D.psi[0][1], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], tx2);
+    if (D.psi[1][0]) cpml4<T>(D.psi[1][0], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], ty1);
+    if (D.psi[1][1]) cpml4<T>(D.psi[1][1], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], ty2);
+    if (D.psi[2][0]) cpml4<T>(D.psi[2][0], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], tz1);
+    if (D.psi[2][1]) cpml4<T>(D.psi[2][1], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tz2);
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    const double ce = a.dt * D.inv_eps;
+    double ox[4], oy[4], oz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        ox[e] = lane4<T>(ex, e) + ce * (tx1[e] - tx2[e]) - source_term(a, amp, 0, i, j, k + e);
+        oy[e] = lane4<T>(ey, e) + ce * (ty1[e] - ty2[e]) - source_term(a, amp, 1, i, j, k + e);
+        oz[e] = lane4<T>(ez, e) + ce * (tz1[e] - tz2[e]) - source_term(a, amp, 2, i, j, k + e);
     }
     V wx, wy, wz;
     wx.x = (T)ox[0]; wx.y = (T)ox[1]; wx.z = (T)ox[2]; wx.w = (T)ox[3];
     wy.x = (T)oy[0]; wy.y = (T)oy[1]; wy.z = (T)oy[2]; wy.w = (T)oy[3];
     wz.x = (T)oz[0]; wz.y = (T)oz[1]; wz.z = (T)oz[2]; wz.w = (T)oz[3];
-    *Hx = wx;
-    *Hy = wy;
-    *Hz = wz;
+    *Ex = wx;
+    *Ey = wy;
+    *Ez = wz;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -877,6 +998,12 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
 
 template <int DIM, typename T>
 static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int ng, bool pml, bool energy, hipStream_t s) {
+    if (DIM == 3 && kind == K_BACKGROUND && a.nrd < 0) {   // z-vectorized launch over the table's regions
+        const long long n = (long long)a.ext[0] * a.ext12;
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_update_e3_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     if (kind == K_BACKGROUND)
         return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, ch, energy, s)
                    : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, ch, energy, s);
@@ -934,8 +1061,8 @@ template <int DIM, typename T>
 static hipError_t launch_h_dim(const HArgs &a, bool pml, hipStream_t s) {
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
-    if (DIM == 3 && !pml && a.lo[2] % 4 == 0 && a.ext[2] % 4 == 0 && a.n[2] % 4 == 0) {
-        hipLaunchKernelGGL(k_update_h3_v4<T>, dim3(nblocks(n / 4)), dim3(kBlock), 0, s, a);
+    if (DIM == 3 && a.nrd < 0) {       // z-vectorized launch: the table holds the regions, ext[0] the threads
+        hipLaunchKernelGGL(k_update_h3_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     if (pml)

@@ -95,7 +95,7 @@ struct Region {
 // launches replace many small launches whose cost is mostly launch latency)
 struct Launch {
     std::vector<int> regs;
-    bool grouped = false, pml = false, energy = false;
+    bool grouped = false, v4 = false, pml = false, energy = false;
     long long blocks = 0, cells = 0, block_base = 0;
     RegionTable *rd = nullptr;
 };
@@ -454,8 +454,9 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     for (auto &r : g->regions)
         for (auto &e : g->ens)
             if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
-    auto blocks_of = [](const Region &r) { return (r.cells() + kBlock - 1) / kBlock; };
-    auto make = [&](std::vector<Launch> &out, const std::vector<Region> &rs, const std::vector<int> &idx, bool group) {
+    auto blocks_of = [](const Region &r, bool v4) { return ((v4 ? r.cells() / 4 : r.cells()) + kBlock - 1) / kBlock; };
+    auto make = [&](std::vector<Launch> &out, const std::vector<Region> &rs, const std::vector<int> &idx, bool group,
+                    bool v4) {
         for (size_t s = 0; s < idx.size();) {
             Launch L;
             const size_t n = group ? std::min<size_t>(kMaxGroup, idx.size() - s) : 1;
@@ -464,28 +465,34 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
                 L.regs.push_back(idx[s + q]);
                 L.pml |= rg.pml_mask != 0;
                 L.energy |= rg.energy;
-                L.blocks += blocks_of(rg);
+                L.blocks += blocks_of(rg, v4);
                 L.cells += rg.cells();
             }
             L.grouped = n > 1;
+            L.v4 = v4;
             out.push_back(L);
             s += n;
         }
     };
+    // 3D regions whose z range is 4-aligned take the z-vectorized kernels
+    auto z4 = [&](const Region &rg) {
+        return g->ndim == 3 && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 && g->n[2] % 4 == 0;
+    };
     {
-        std::vector<int> bg, solo;
-        for (int i = 0; i < (int)g->regions.size(); i++) (g->regions[i].mat < 0 ? bg : solo).push_back(i);
-        make(g->elaunch, g->regions, bg, bg.size() > 1);
-        make(g->elaunch, g->regions, solo, false);
-        std::vector<int> hg, hv;
-        for (int i = 0; i < (int)g->hregions.size(); i++) {
-            const Region &rg = g->hregions[i];
-            const bool v4 = g->ndim == 3 && !rg.pml_mask && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 &&
-                            g->n[2] % 4 == 0;
-            (v4 ? hv : hg).push_back(i);
+        std::vector<int> bg4, bg, solo;
+        for (int i = 0; i < (int)g->regions.size(); i++) {
+            const Region &rg = g->regions[i];
+            if (rg.mat >= 0) solo.push_back(i);
+            else if (z4(rg) && !rg.energy) bg4.push_back(i);
+            else bg.push_back(i);
         }
-        make(g->hlaunch, g->hregions, hg, hg.size() > 1);
-        make(g->hlaunch, g->hregions, hv, false);
+        make(g->elaunch, g->regions, bg4, true, true);
+        make(g->elaunch, g->regions, bg, bg.size() > 1, false);
+        make(g->elaunch, g->regions, solo, false, false);
+        std::vector<int> h4, hg;
+        for (int i = 0; i < (int)g->hregions.size(); i++) (z4(g->hregions[i]) ? h4 : hg).push_back(i);
+        make(g->hlaunch, g->hregions, h4, true, true);
+        make(g->hlaunch, g->hregions, hg, hg.size() > 1, false);
     }
     long long base = 0;
     for (auto &L : g->elaunch) {
@@ -495,7 +502,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     g->total_blocks = base;
     for (int ph = 0; ph < 2; ph++)
         for (auto &L : ph ? g->hlaunch : g->elaunch) {
-            if (!L.grouped) continue;
+            if (!L.grouped && !L.v4) continue;
             const std::vector<Region> &rs = ph ? g->hregions : g->regions;
             RegionTable tab{};
             for (int s = 0; s < kMaxGroup; s++) tab.block0[s] = INT_MAX;
@@ -507,7 +514,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
                 x.ext12 = x.ext[1] * x.ext[2];
                 x.block0 = b0;
                 tab.block0[q] = b0;
-                b0 += (int)blocks_of(rg);
+                b0 += (int)blocks_of(rg, L.v4);
                 x.inv_eps = 1.0 / rg.eps;
                 for (int c = 0; c < 3; c++)
                     for (int t = 0; t < 2; t++) x.psi[c][t] = ph ? rg.psiH[c][t] : rg.psiE[c][t];
@@ -619,12 +626,12 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         a.ext12 = a.ext[1] * a.ext[2];
         a.dt = g->dt;
         a.inv_eps = 1.0 / r.eps;
-        if (L.grouped) {
+        if (L.grouped || L.v4) {
             for (int ax = 0; ax < 3; ax++) { a.lo[ax] = 0; a.ext[ax] = 1; }
             a.ext[0] = (int)(L.blocks * kBlock);
             a.ext12 = 1;
             a.rd = L.rd;
-            a.nrd = (int)L.regs.size();
+            a.nrd = L.v4 ? -(int)L.regs.size() : (int)L.regs.size();
         }
         int kind = K_BACKGROUND, ng = 0;
         for (int c = 0; c < 3; c++)
@@ -705,12 +712,12 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         for (int c = 0; c < 3; c++)
             for (int t = 0; t < 2; t++) a.psi[c][t] = r.psiH[c][t];
         for (int ax = 0; ax < 3; ax++) { a.pml_b[ax] = g->pml_bh[ax]; a.pml_c[ax] = g->pml_ch[ax]; }
-        if (L.grouped) {
+        if (L.grouped || L.v4) {
             for (int ax = 0; ax < 3; ax++) { a.lo[ax] = 0; a.ext[ax] = 1; }
             a.ext[0] = (int)(L.blocks * kBlock);
             a.ext12 = 1;
             a.rd = L.rd;
-            a.nrd = (int)L.regs.size();
+            a.nrd = L.v4 ? -(int)L.regs.size() : (int)L.regs.size();
         }
         const int rec = (int)g->elaunch.size() + (int)(&L - &g->hlaunch[0]);
         Pending pe{rec, nullptr, nullptr};
