@@ -249,6 +249,79 @@ def bench_closure2d(args):
     }), flush=True)
 
 
+def bench_large3d(args):
+    """The 512^3 grid (Lorentz-Bath slab over 40 % of z, N_b = 16 Ohmic): explicit bath vs learned closure,
+    cell-updates/s of both and the closure's errors against the explicit run on a 64 x 64 x 512 crop."""
+    import numpy as np
+    import torch
+    from fdtdb_inputs import configs
+    from fdtdb_inputs.philox import Stream
+    from paper_2505_23963_amd import Grid, closure
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    s = stream.cuda_stream
+    steps = args.steps
+    # closure trained on a 32 x 32 crop of the same layout (Ex trajectories of 8192 bath cells)
+    rec = configs.config5_3d_large(nx=32, ny=32)
+    ncell = 32 * 32 * 205
+    cells = np.unique(Stream(1005, 5).integers(11000, 0, ncell - 1))[:8192]
+    t0 = time.perf_counter()
+    E, P = closure.record(rec, 0, 0, cells, 1024, stream=s)
+    res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), stream=s)
+    t_train = time.perf_counter() - t0
+    cl = {0: {"weights": res["weights"], "scales": res["scales"]}}
+    p = configs.config5_3d_large()
+
+    def timed(closures=None):
+        g = Grid(p, stream=s, closures=closures)
+        g.step(args.warmup)
+        g.synchronize()
+        g.set_profiling(True, dispersive_only=True)
+        g.kernel_records()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(steps)
+        g.synchronize()
+        dt = time.perf_counter() - t
+        recs = g.kernel_records()
+        lb = max((r for r in recs if r["phase"] == 0), key=lambda r: r["ms_total"])
+        out = (p.cells * steps / dt / 1e9, dt / steps * 1e3, lb["ms_total"] / max(lb["launches"], 1), lb["bytes"])
+        del g
+        return out
+
+    print("[bench] explicit 512^3", file=sys.stderr, flush=True)
+    v_exp, ms_exp, k_exp, b_exp = timed()
+    print("[bench] closure 512^3", file=sys.stderr, flush=True)
+    v_cl, ms_cl, k_cl, _ = timed(cl)
+    errs = {}
+    pc = configs.config5_3d_large(nx=64, ny=64)
+    for horizon in (1200, 4000):
+        ge = Grid(pc, stream=s)
+        ge.step(horizon)
+        fe, ee = ge.flux(0), ge.field(0)
+        del ge
+        gc = Grid(pc, stream=s, closures=cl)
+        gc.step(horizon)
+        fc, ec = gc.flux(0), gc.field(0)
+        del gc
+        errs[str(horizon)] = {"spectral": float(np.max(np.abs(fc - fe)) / np.max(np.abs(fe))),
+                              "field": float(np.linalg.norm(ec - ee) / np.linalg.norm(ee))}
+    print(json.dumps({
+        "metric": METRIC, "value": round(v_exp, 4), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_exp, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D 512x512x512, periodic x,y, CPML z, 205-cell Lorentz-Bath slab (N_b=16 Ohmic), "
+                               "Gaussian-profile plane source, 256-frequency FP64 z-flux plane", "cells": p.cells,
+                   "state_dtype": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(b_exp / (k_exp * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(b_exp / (k_exp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "kernel": "E_lorentz_bath_nb16", "avg_launch_ms": round(k_exp, 4), "bytes_per_launch": b_exp},
+        "learned": {"value": round(v_cl, 4), "ms_per_step": round(ms_cl, 4), "slab_kernel_ms": round(k_cl, 4),
+                    "learned_over_explicit": round(v_cl / v_exp, 3), "training_seconds": round(t_train, 1),
+                    "loss_linear": res["loss_linear"], "errors_vs_explicit_64x64_crop": errs},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,7 +333,7 @@ def main():
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d"], default="planar3d",
+    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d", "large3d"], default="planar3d",
                     help="planar3d: the default 256x256x512 line; cavities: the 64-cavity batched 1D workload; "
                          "closure2d: learned closure vs explicit bath on the 2D 2048^2 grid")
     args = ap.parse_args()
@@ -280,6 +353,9 @@ def main():
         return
     if args.workload == "closure2d":
         bench_closure2d(args)
+        return
+    if args.workload == "large3d":
+        bench_large3d(args)
         return
 
     import torch

@@ -238,3 +238,34 @@ def test_validator_drude_bound_matches_propagator(oracle_lib, eps_factor, ok):
     else:
         with pytest.raises(FdtdbError):
             Grid(p)
+
+
+def test_config2_full_size_sampled(oracle_lib):
+    """The full 256 x 256 x 512 workload in the launch configuration the benchmark times, checked on
+    sampled columns: after N steps a cell depends only on cells within N cells of it (each half step
+    reaches one neighbour), so the oracle on a periodic crop with a margin of N + 2 cells around the
+    sampled columns (same sigma window) gives exactly their values."""
+    from paper_2505_23963_amd import Grid
+    N, c = 24, 2
+    p = configs.config2_3d(steps=0, nfreq=16)
+    print(f"[gpu] config2 full size {p.n} f32, {N} steps", flush=True)
+    g = Grid(p)
+    g.step(N)
+    full = {comp: g.field(comp) for comp in range(6)}
+    pg = g.polarization(1, 0)
+    h = N + 2 + c
+    for xc, yc in ((0, 0), (137, 201)):
+        crop = configs.config2_3d(nx=2 * h, ny=2 * h, steps=0, nfreq=16, dtype="f64", sigma_window=(xc - h, yc - h))
+        o = oracle_lib.run(crop, steps=N)
+        xs = (xc + np.arange(-c, c)) % 256
+        ys = (yc + np.arange(-c, c)) % 256
+        big = max(np.max(np.abs(full[comp][xs][:, ys])) for comp in range(6))
+        assert big > 0
+        for comp in range(6):
+            ref = o.field(comp)[h - c:h + c, h - c:h + c]
+            got = full[comp][xs][:, ys]
+            err = np.max(np.abs(got - ref)) / big
+            assert err < 1e-5, (xc, yc, comp, err)
+        po = o.polarization(1, 0).reshape(2 * h, 2 * h, 400)[h - c:h + c, h - c:h + c]
+        pgg = pg.reshape(256, 256, 400)[xs][:, ys]
+        assert np.max(np.abs(pgg - po)) <= 1e-5 * np.max(np.abs(po)) + 1e-30
