@@ -38,10 +38,16 @@ KIND = {0: "background", 1: "drude", 2: "lorentz_bath", 3: "closure"}
 
 
 def source_hash() -> str:
-    """Hash of the kernel sources (the files the profiled kernels are compiled from)."""
+    """Hash of the dominant kernel's source text (the Lorentz-Bath E kernel and the helpers it calls),
+    so that counters taken on it stay valid while other kernels change."""
+    src = open(os.path.join(ROOT, "paper_2505_23963_amd", "csrc", "fdtdb_kernels.hip")).read()
     h = hashlib.sha256()
-    for name in ("fdtdb_kernels.hip", "fdtdb_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2505_23963_amd", "csrc", name), "rb").read())
+    for start in ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
+                  "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
+                  "__device__ __forceinline__ void unflatten(", "void k_update_e_bath(const EArgs a"):
+        s = src.find(start)
+        e = src.find("\n}\n", s)
+        h.update(src[s:e].encode() if s >= 0 else start.encode())
     return h.hexdigest()[:16]
 
 
