@@ -10,7 +10,7 @@ constexpr int kMaxSources = 4;
 constexpr int kMaxModes = 64;
 constexpr int kMaxEnergy = 4;
 constexpr int kBlock = 256;          // threads per block of the stencil kernels
-constexpr int kDftSlots = 32;        // steps staged before a DFT flush
+constexpr int kDftSlots = 64;        // steps staged before a DFT flush
 constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
 
 // Update kind of a region.

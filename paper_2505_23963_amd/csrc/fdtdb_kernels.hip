@@ -524,8 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
             const V4 *Yp = static_cast<const V4 *>(a.Ynew[c]);
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-                yc[ci][g] = __builtin_nontemporal_load(Yc + g * mcells + m);
-                yp[ci][g] = __builtin_nontemporal_load(Yp + g * mcells + m);
+                yc[ci][g] = __builtin_nontemporal_load(Yc + (long long)g * mcells + m);
+                yp[ci][g] = __builtin_nontemporal_load(Yp + (long long)g * mcells + m);
             }
         }
         double amp[kMaxSources];
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
                 for (int u = 0; u < 4; ++u) r[u] = cf.md[4 * g + u][0] * yv0[u] + cf.md[4 * g + u][1] * yv1[u] + cf.md[4 * g + u][2] * dP;
                 V4 o;
                 o.x = (T)r[0]; o.y = (T)r[1]; o.z = (T)r[2]; o.w = (T)r[3];
-                __builtin_nontemporal_store(o, Yn + g * mcells + m);
+                __builtin_nontemporal_store(o, Yn + (long long)g * mcells + m);
             }
             if (ENERGY && sample) {
                 ef += 0.5 / a.inv_eps * Eo[ci] * En;
@@ -751,11 +751,12 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// 3D E update of background regions (vacuum, dielectric, CPML), four z-consecutive cells per
-// thread, regions from the launch's table (no energy sampling: launches with monitors take the
-// generic kernel).
+// 3D E update of background regions (vacuum, dielectric, CPML) or of a Drude region (DRUDE:
+// the polarization increment V = P^{n+1/2} - P^{n-1/2} read and written in the same pass), four
+// z-consecutive cells per thread, regions from the launch's table (no energy sampling: launches
+// with monitors take the generic kernel).
 // ---------------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool DRUDE>
 __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     using V = vec4_t<T>;
     Cell4 C;
@@ -807,11 +808,36 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     load_amps(a, amp);
     const double ce = a.dt * D.inv_eps;
     double ox[4], oy[4], oz[4];
+    if (DRUDE) {
+        // Drude: E^{n+1/2} = E^{n-1/2} + (dt curl H - V) / eps - dt J / eps;  V' = dE E^{n+1/2} + dV V
+        const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+        const double dE = a.coef[0], dV = a.coef[1];
+        double *o3[3] = {ox, oy, oz};
+        const V *ev[3] = {&ex, &ey, &ez};
+        double *t1s[3] = {tx1, ty1, tz1}, *t2s[3] = {tx2, ty2, tz2};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        ox[e] = lane4<T>(ex, e) + ce * (tx1[e] - tx2[e]) - source_term(a, amp, 0, i, j, k + e);
-        oy[e] = lane4<T>(ey, e) + ce * (ty1[e] - ty2[e]) - source_term(a, amp, 1, i, j, k + e);
-        oz[e] = lane4<T>(ez, e) + ce * (tz1[e] - tz2[e]) - source_term(a, amp, 2, i, j, k + e);
+        for (int c = 0; c < 3; ++c) {
+            nvec4_t<T> *Vp = reinterpret_cast<nvec4_t<T> *>(static_cast<T *>(a.Pcur[c]) + m);
+            const nvec4_t<T> vv = __builtin_nontemporal_load(Vp);
+            nvec4_t<T> vn;
+            double vo[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double v = (double)vv[e];
+                o3[c][e] = lane4<T>(*ev[c], e) + D.inv_eps * (a.dt * (t1s[c][e] - t2s[c][e]) - v) -
+                           source_term(a, amp, c, i, j, k + e);
+                vo[e] = dE * o3[c][e] + dV * v;
+            }
+            vn[0] = (T)vo[0]; vn[1] = (T)vo[1]; vn[2] = (T)vo[2]; vn[3] = (T)vo[3];
+            __builtin_nontemporal_store(vn, Vp);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            ox[e] = lane4<T>(ex, e) + ce * (tx1[e] - tx2[e]) - source_term(a, amp, 0, i, j, k + e);
+            oy[e] = lane4<T>(ey, e) + ce * (ty1[e] - ty2[e]) - source_term(a, amp, 1, i, j, k + e);
+            oz[e] = lane4<T>(ez, e) + ce * (tz1[e] - tz2[e]) - source_term(a, amp, 2, i, j, k + e);
+        }
     }
     V wx, wy, wz;
     wx.x = (T)ox[0]; wx.y = (T)ox[1]; wx.z = (T)ox[2]; wx.w = (T)ox[3];
@@ -998,10 +1024,13 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
 
 template <int DIM, typename T>
 static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int ng, bool pml, bool energy, hipStream_t s) {
-    if (DIM == 3 && kind == K_BACKGROUND && a.nrd < 0) {   // z-vectorized launch over the table's regions
+    if (DIM == 3 && (kind == K_BACKGROUND || kind == K_DRUDE) && a.nrd < 0) {   // z-vectorized launch
         const long long n = (long long)a.ext[0] * a.ext12;
         if (n == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_update_e3_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        if (kind == K_DRUDE)
+            hipLaunchKernelGGL((k_update_e3_v4<T, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_update_e3_v4<T, false>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     if (kind == K_BACKGROUND)

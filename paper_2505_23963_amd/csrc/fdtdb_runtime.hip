@@ -479,15 +479,22 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         return g->ndim == 3 && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 && g->n[2] % 4 == 0;
     };
     {
-        std::vector<int> bg4, bg, solo;
+        std::vector<int> bg4, bg, solo, drude4;
         for (int i = 0; i < (int)g->regions.size(); i++) {
             const Region &rg = g->regions[i];
-            if (rg.mat >= 0) solo.push_back(i);
-            else if (z4(rg) && !rg.energy) bg4.push_back(i);
-            else bg.push_back(i);
+            if (rg.mat >= 0) {
+                const Material &mt = g->mats[rg.mat];
+                const bool m4 = mt.mext[2] % 4 == 0 && (rg.lo[2] - (int)mt.lo[2]) % 4 == 0;
+                (mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy ? drude4 : solo).push_back(i);
+            } else if (z4(rg) && !rg.energy) {
+                bg4.push_back(i);
+            } else {
+                bg.push_back(i);
+            }
         }
         make(g->elaunch, g->regions, bg4, true, true);
         make(g->elaunch, g->regions, bg, bg.size() > 1, false);
+        make(g->elaunch, g->regions, drude4, false, true);
         make(g->elaunch, g->regions, solo, false, false);
         std::vector<int> h4, hg;
         for (int i = 0; i < (int)g->hregions.size(); i++) (z4(g->hregions[i]) ? h4 : hg).push_back(i);
