@@ -187,13 +187,16 @@ def bench_closure2d(args):
     torch.cuda.init()
     stream = torch.cuda.Stream()
     s = stream.cuda_stream
-    # training data: the same material on a 256^2 grid, 8192 recorded cells, 1024 steps
-    rec = configs.config4_2d(n=256, patch=(64, 192), src_x=56, flux_x=208)
-    cells = np.unique(Stream(1004, 5).integers(11000, 0, 128 * 128 - 1))[:8192]
+    # training data: the same material on a 512^2 grid (256^2 patch), every patch cell recorded for 1024 steps:
+    # 65536 trajectories x 16 windows of 64 steps = 1.05e6 windows per epoch
+    rec = configs.config4_2d(n=512, patch=(128, 384), src_x=120, flux_x=400)
+    cells = np.arange(256 * 256)
     t0 = time.perf_counter()
     E, P = closure.record(rec, 0, 2, cells, 1024, stream=s)
     res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), stream=s)
     t_train = time.perf_counter() - t0
+    # multiply-adds per window-step: forward 1408, backward 1312, weight gradients 1477
+    train_flops = 2.0 * (1408 + 1312 + 1477) * len(cells) * 1024 * len(res["curve"])
     print(f"[bench] closure trained in {t_train:.1f} s: loss {res['loss_tanh']:.3e}", file=sys.stderr, flush=True)
     p = configs.config4_2d()
     steps = args.steps if args.steps != 64 else 2000
@@ -214,6 +217,8 @@ def bench_closure2d(args):
         return p.cells * steps / dt / 1e9, dt / steps * 1e3, lb["ms_total"] / max(lb["launches"], 1), g
 
     v_exp, ms_exp, k_exp, _ = timed()
+    bx = p.materials[0].box
+    patch_cells = int(np.prod([bx[1][a] - bx[0][a] for a in range(3)]))
     cl = {0: {"weights": res["weights"], "scales": res["scales"]}}
     v_cl, ms_cl, k_cl, _ = timed(cl)
     # accuracy over the workload's 10000 steps (and before the explicit bath's revival)
@@ -248,9 +253,17 @@ def bench_closure2d(args):
         "explicit": {"value": round(v_exp, 4), "ms_per_step": round(ms_exp, 4), "patch_kernel_ms": round(k_exp, 4)},
         "learned": {"value": round(v_cl, 4), "ms_per_step": round(ms_cl, 4), "patch_kernel_ms": round(k_cl, 4)},
         "learned_over_explicit": round(v_cl / v_exp, 3),
-        "training": {"seconds": round(t_train, 2), "loss_linear": res["loss_linear"], "loss_tanh": res["loss_tanh"],
-                     "trajectories": res["trajectories"], "steps": 1024, "window": 64,
-                     "adam_steps": len(res["curve"]) * res["windows_per_epoch"]},
+        "learned_kernel_roofline": {"bound": "alu", "achieved": round(patch_cells * 2816 / (k_cl * 1e-3) / 1e12, 2),
+                                    "peak": 157.3, "unit": "TFLOP/s",
+                                    "frac": round(patch_cells * 2816 / (k_cl * 1e-3) / 1e12 / 157.3, 4),
+                                    "flops_per_cell": 2816},
+        "training": {"seconds": round(res["train_seconds"], 2), "loss_linear": res["loss_linear"],
+                     "loss_tanh": res["loss_tanh"], "trajectories": res["trajectories"], "steps": 1024, "window": 64,
+                     "windows_per_epoch": res["trajectories"] * res["windows_per_epoch"],
+                     "adam_steps": len(res["curve"]) * res["windows_per_epoch"],
+                     "roofline": {"bound": "alu", "achieved": round(train_flops / res["train_seconds"] / 1e12, 2),
+                                  "peak": 157.3, "unit": "TFLOP/s",
+                                  "frac": round(train_flops / res["train_seconds"] / 1e12 / 157.3, 4)}},
         "errors_vs_explicit": out_err,
     }), flush=True)
 
