@@ -21,6 +21,17 @@ enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3 };
 constexpr int kClosureWidth = 32;
 constexpr int kClosureParams = 32 * 7 + 32 + 32 * 32 + 32 + 5 * 32 + 5;
 
+// Position of weight e in the transposed copy kept next to the weights: W1T[7][32], b1, W2T[32][32],
+// b2, W3T[32][5], b3 (same block offsets).  Loops over an input feature with all output units as
+// independent accumulators read one contiguous row of the transposed copy per feature.
+__host__ __device__ inline int closure_tpos(int e) {
+    constexpr int W = 32, B1 = W * 7, W2 = B1 + W, B2 = W2 + W * W, W3 = B2 + W, B3 = W3 + 5 * W;
+    if (e < B1) return (e % 7) * W + e / 7;
+    if (e >= W2 && e < B2) return W2 + ((e - W2) % W) * W + (e - W2) / W;
+    if (e >= W3 && e < B3) return W3 + ((e - W3) % W) * 5 + (e - W3) / W;
+    return e;
+}
+
 // tanh in FP32: odd Taylor series below |a| = 1/16 (no transcendental; a wave whose lanes are all
 // in range skips the exponential), 1 - 2 / (1 + e^{2a}) above (absolute error about 1e-7;
 // saturates to +-1 for large |a|).  Shared by closure inference and training.

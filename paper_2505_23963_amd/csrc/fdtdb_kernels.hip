@@ -202,8 +202,9 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
     const bool live = t0 < ncell;
     const int t = live ? t0 : ncell - 1;
     constexpr int W = kClosureWidth;
-    const cfptr w = (cfptr)a.cw;
-    const cfptr W1 = w, b1 = W1 + W * 7, W3 = b1 + W + W * W + W, b3 = W3 + 5 * W;
+    // layers 1 and 3 read the transposed copy (one contiguous row per input feature)
+    const cfptr wt = (cfptr)(a.cw + kClosureParams);
+    const cfptr W1T = wt, b1 = W1T + W * 7, W3T = b1 + W + W * W + W, b3 = W3T + 5 * W;
     // layer-2 operands of this lane: A = W2 rows 16 h + (lane mod 16), columns 4 s + lane / 16;
     // accumulator start = b2 of units 16 h + 4 (lane / 16) + v
     const float *W2 = a.cw + W * 7 + W;
@@ -258,12 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
         // layer 1 (vector ALU), z1 row to LDS
         float z1[W];
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-            float s = b1[u];
+        for (int u = 0; u < W; ++u) z1[u] = b1[u];
 #pragma unroll
-            for (int v = 0; v < 7; ++v) s = fmaf(W1[u * 7 + v], x[v], s);
-            z1[u] = s;
-            if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
+        for (int v = 0; v < 7; ++v) {
+#pragma unroll
+            for (int u = 0; u < W; ++u) z1[u] = fmaf(W1T[v * W + u], x[v], z1[u]);
+            __asm__ volatile("" ::: "memory");
         }
         tanh_n<W>(z1);
 #pragma unroll
@@ -298,12 +299,12 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
         __syncthreads();
         float o[5];
 #pragma unroll
-        for (int u = 0; u < 5; ++u) {
-            float s = b3[u];
+        for (int q = 0; q < 5; ++q) o[q] = b3[q];
 #pragma unroll
-            for (int v = 0; v < W; ++v) s = fmaf(W3[u * W + v], z2[v], s);
-            o[u] = s;
-            __asm__ volatile("" ::: "memory");
+        for (int u = 0; u < W; ++u) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) o[q] = fmaf(W3T[u * 5 + q], z2[u], o[q]);
+            if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
         }
         const double force = (double)o[4] * a.cscale[3];
         const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - force * cf[5];

@@ -1014,8 +1014,14 @@ fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *
     for (int q = 0; q < kClosureParams; q++)
         if (!std::isfinite(weights[q])) return fail(FDTDB_E_INVALID, "non-finite closure weight");
     Material &m = g->mats[material_id];
-    if (!m.cw_dev) TRY(g->alloc((void **)&m.cw_dev, sizeof(float) * kClosureParams));
-    HIP_TRY(hipMemcpy(m.cw_dev, weights, sizeof(float) * kClosureParams, hipMemcpyHostToDevice));
+    // the weights, then their transposed copy (layers 1 and 3 of the inference kernel read it)
+    if (!m.cw_dev) TRY(g->alloc((void **)&m.cw_dev, 2 * sizeof(float) * kClosureParams));
+    std::vector<float> both(2 * (size_t)kClosureParams);
+    for (int e = 0; e < kClosureParams; e++) {
+        both[e] = weights[e];
+        both[kClosureParams + closure_tpos(e)] = weights[e];
+    }
+    HIP_TRY(hipMemcpy(m.cw_dev, both.data(), 2 * sizeof(float) * kClosureParams, hipMemcpyHostToDevice));
     for (int c = 0; c < 3; c++)
         if (e_active(g->ndim, c) && !m.hid[c]) TRY(g->alloc(&m.hid[c], 16 * (size_t)m.mcells));
     m.cscale[0] = scales[0];

@@ -166,9 +166,11 @@ __global__ __launch_bounds__(TB) void k_pack(const float *Erec, const float *Pre
 
 // ------------------------------------------------------------------------------- forward / backward
 template <int ACT>
-__global__ __launch_bounds__(TB) void k_forward(const float *X, const float *Y, const float *w_, float4 *hcarry,
+__global__ __launch_bounds__(TB) void k_forward(const float *X, const float *Y, const float *wt_, float4 *hcarry,
                                                 float *act, float *res, double *lossp, long long N, int W, long long t0) {
-    const cfp w = (cfp)w_;
+    // weights in the transposed layout: one contiguous row per input feature, every output unit an
+    // independent accumulator
+    const cfp w = (cfp)wt_;
     const long long i = blockIdx.x * (long long)TB + threadIdx.x;
     const bool live = i < N;
     double lsum = 0.0;
@@ -182,31 +184,35 @@ __global__ __launch_bounds__(TB) void k_forward(const float *X, const float *Y, 
             for (int v = 0; v < NIN; ++v) ar[(A_X + v) * N] = x[v];
             float z1[WID], z2[WID];
 #pragma unroll
-            for (int u = 0; u < WID; ++u) {
-                float s = w[P_B1 + u];
+            for (int u = 0; u < WID; ++u) z1[u] = w[P_B1 + u];
 #pragma unroll
-                for (int v = 0; v < NIN; ++v) s = fmaf(w[P_W1 + u * NIN + v], x[v], s);
-                z1[u] = act_f<ACT>(s);
-                ar[(A_Z1 + u) * N] = z1[u];
-                if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
+            for (int v = 0; v < NIN; ++v) {
+#pragma unroll
+                for (int u = 0; u < WID; ++u) z1[u] = fmaf(w[P_W1 + v * WID + u], x[v], z1[u]);
+                __asm__ volatile("" ::: "memory");
             }
 #pragma unroll
             for (int u = 0; u < WID; ++u) {
-                float s = w[P_B2 + u];
+                z1[u] = act_f<ACT>(z1[u]);
+                ar[(A_Z1 + u) * N] = z1[u];
+                z2[u] = w[P_B2 + u];
+            }
 #pragma unroll
-                for (int v = 0; v < WID; ++v) s = fmaf(w[P_W2 + u * WID + v], z1[v], s);
-                z2[u] = act_f<ACT>(s);
-                ar[(A_Z2 + u) * N] = z2[u];
+            for (int v = 0; v < WID; ++v) {
+#pragma unroll
+                for (int u = 0; u < WID; ++u) z2[u] = fmaf(w[P_W2 + v * WID + u], z1[v], z2[u]);
                 __asm__ volatile("" ::: "memory");
             }
             float o[NOUT];
 #pragma unroll
-            for (int k = 0; k < NOUT; ++k) {
-                float s = w[P_B3 + k];
+            for (int k = 0; k < NOUT; ++k) o[k] = w[P_B3 + k];
 #pragma unroll
-                for (int v = 0; v < WID; ++v) s = fmaf(w[P_W3 + k * WID + v], z2[v], s);
-                o[k] = s;
-                __asm__ volatile("" ::: "memory");
+            for (int u = 0; u < WID; ++u) {
+                z2[u] = act_f<ACT>(z2[u]);
+                ar[(A_Z2 + u) * N] = z2[u];
+#pragma unroll
+                for (int k = 0; k < NOUT; ++k) o[k] = fmaf(w[P_W3 + u * NOUT + k], z2[u], o[k]);
+                if ((u & 3) == 3) __asm__ volatile("" ::: "memory");
             }
             const float r = o[4] - Y[(t0 + t) * N + i];
             res[(long long)t * N + i] = r;
@@ -279,75 +285,144 @@ __global__ __launch_bounds__(TB) void k_backward(const float *w_, const float *a
     }
 }
 
-// parameter e -> (delta row, activation row); activation row NACT is the constant 1 (biases)
-__device__ __forceinline__ void param_rows(int e, int &dq, int &aq) {
-    if (e < P_B1) { dq = D_A1 + e / NIN; aq = A_X + e % NIN; }
-    else if (e < P_W2) { dq = D_A1 + (e - P_B1); aq = NACT; }
-    else if (e < P_B2) { const int f = e - P_W2; dq = D_A2 + f / WID; aq = A_Z1 + f % WID; }
-    else if (e < P_W3) { dq = D_A2 + (e - P_B2); aq = NACT; }
-    else if (e < P_B3) { const int f = e - P_W3; dq = D_O + f / WID; aq = A_Z2 + f % WID; }
-    else { dq = D_O + (e - P_B3); aq = NACT; }
+// Weight gradients: every parameter block is an outer product of a delta vector and an activation
+// vector (+ a constant-1 column for the biases) summed over samples (window steps x trajectories).
+// A tile of 64 samples is staged in LDS sample-major (72 floats per sample: activations
+// [x0..x6, 1, z1, z2], deltas [do0..4, 0, 0, 0, da2, da1]), and each thread owns a 4 x 4 block of
+// one product: per sample one 16-byte read of 4 deltas, one of 4 activations, 16 FMAs.  FP32 sums
+// per tile, FP64 across tiles; the two halves of the block take alternate halves of the samples.
+constexpr int SROW = 76;           // LDS floats per sample (72 used; 16-byte aligned rows)
+constexpr int A_OFF_X = 0, A_OFF_ONE = 7, A_OFF_Z1 = 8, A_OFF_Z2 = 40;
+constexpr int D_OFF_O = 0, D_OFF_A2 = 8, D_OFF_A1 = 40;
+constexpr int NTASK = 106;         // 4 x 4 tasks: W1|b1 16, W2 64, b2 8, W3 16, b3 2
+
+struct Task {
+    int doff, aoff;                // offsets of the 4 deltas / 4 activations in an LDS sample row
+    int kind, r0, c0;              // 0: W1|b1, 1: W2, 2: b2, 3: W3, 4: b3; first row / column
+};
+__device__ __forceinline__ Task task_of(int id) {
+    Task k;
+    if (id < 16) { k.kind = 0; k.r0 = 4 * (id >> 1); k.c0 = 4 * (id & 1); k.doff = D_OFF_A1 + k.r0; k.aoff = A_OFF_X + k.c0; }
+    else if (id < 80) { const int q = id - 16; k.kind = 1; k.r0 = 4 * (q >> 3); k.c0 = 4 * (q & 7); k.doff = D_OFF_A2 + k.r0; k.aoff = A_OFF_Z1 + k.c0; }
+    else if (id < 88) { const int q = id - 80; k.kind = 2; k.r0 = 4 * q; k.c0 = 0; k.doff = D_OFF_A2 + k.r0; k.aoff = 4; }
+    else if (id < 104) { const int q = id - 88; k.kind = 3; k.r0 = 4 * (q >> 3); k.c0 = 4 * (q & 7); k.doff = D_OFF_O + k.r0; k.aoff = A_OFF_Z2 + k.c0; }
+    else { const int q = id - 104; k.kind = 4; k.r0 = 4 * q; k.c0 = 0; k.doff = D_OFF_O + k.r0; k.aoff = 4; }
+    return k;
+}
+// parameter index of (r, c) of a task's 4 x 4 block, or -1 for padding
+__device__ __forceinline__ int task_param(const Task &k, int r, int c) {
+    const int row = k.r0 + r, col = k.c0 + c;
+    switch (k.kind) {
+        case 0: return col < 7 ? P_W1 + row * NIN + col : P_B1 + row;          // column 7 is the constant 1
+        case 1: return P_W2 + row * WID + col;
+        case 2: return c == 3 ? P_B2 + row : -1;                               // activation offset 4 + 3 = the 1
+        case 3: return row < NOUT ? P_W3 + row * WID + col : -1;
+        default: return (c == 3 && row < NOUT) ? P_B3 + row : -1;
+    }
 }
 
-constexpr int EPT = (NP + TB - 1) / TB;   // parameters per thread
-
-// partial[block][e] = sum over this block's tiles of delta[dq] * act[aq]
+// partial[block][e] = sum over this block's tiles of delta * activation
 __global__ __launch_bounds__(TB) void k_wgrad(const float *act, const float *del, long long N, int W, int tiles_per_block,
                                               double *partial) {
-    __shared__ float sa[(NACT + 1) * LDS_STRIDE];
-    __shared__ float sd[NDEL * LDS_STRIDE];
+    __shared__ float sa[TILE * SROW];
+    __shared__ float sd[TILE * SROW];
+    __shared__ double comb[NTASK][16];
     const long long ntx = (N + TILE - 1) / TILE;
     const long long ntiles = ntx * W;
-    int dq[EPT], aq[EPT];
-    double acc[EPT];
+    const int half = threadIdx.x >> 7, id = threadIdx.x & 127;
+    const bool busy = id < NTASK;
+    const Task K = task_of(busy ? id : 0);
+    double acc[16];
 #pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-        const int e = threadIdx.x + r * TB;
-        if (e < NP) param_rows(e, dq[r], aq[r]);
-        else { dq[r] = 0; aq[r] = NACT; }
-        acc[r] = 0.0;
-    }
-    for (int s = threadIdx.x; s < LDS_STRIDE; s += TB) sa[NACT * LDS_STRIDE + s] = 1.0f;
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    // staging: thread (s = tid mod 64, f0 = tid / 64) moves features f0, f0 + 4, ... of sample s; the next
+    // tile's values are loaded into registers while the current tile is being multiplied
+    constexpr int NST = (NACT + NDEL) * TILE / TB;
+    static_assert((NACT + NDEL) * TILE % TB == 0, "staging split");
+    const int s_me = threadIdx.x & (TILE - 1), f0 = threadIdx.x / TILE;
+    float pre[NST];
+    auto fetch = [&](long long tile) {
+        const long long t = tile / ntx, i = (tile - t * ntx) * TILE + s_me;
+        const bool ok = i < N;
+#pragma unroll
+        for (int r = 0; r < NST; ++r) {
+            const int f = f0 + r * (TB / TILE);
+            const float *src = f < NACT ? act + (t * NACT + f) * N : del + (t * NDEL + (f - NACT)) * N;
+            pre[r] = ok ? src[i] : 0.0f;
+        }
+    };
     const long long first = (long long)blockIdx.x * tiles_per_block;
-    for (long long tile = first; tile < first + tiles_per_block && tile < ntiles; ++tile) {
-        const long long t = tile / ntx, i0 = (tile - t * ntx) * TILE;
-        __syncthreads();
-        for (int id = threadIdx.x; id < (NACT + NDEL) * TILE; id += TB) {
-            const int f = id / TILE, s = id - f * TILE;
-            const long long i = i0 + s;
-            if (f < NACT) sa[f * LDS_STRIDE + s] = i < N ? act[(t * NACT + f) * N + i] : 0.0f;
-            else sd[(f - NACT) * LDS_STRIDE + s] = i < N ? del[(t * NDEL + f - NACT) * N + i] : 0.0f;
-        }
+    const long long last = first + tiles_per_block < ntiles ? first + tiles_per_block : ntiles;
+    if (first < last) fetch(first);
+    for (long long tile = first; tile < last; ++tile) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < EPT; ++r) {
-            const float *pd = sd + dq[r] * LDS_STRIDE, *pa = sa + aq[r] * LDS_STRIDE;
-            float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll 8
-            for (int s = 0; s < TILE; s += 2) {
-                s0 = fmaf(pd[s], pa[s], s0);
-                s1 = fmaf(pd[s + 1], pa[s + 1], s1);
+        for (int r = 0; r < NST; ++r) {
+            const int f = f0 + r * (TB / TILE);
+            if (f < NACT) {
+                const int col = f < NIN ? A_OFF_X + f : (f < A_Z2 ? A_OFF_Z1 + (f - A_Z1) : A_OFF_Z2 + (f - A_Z2));
+                sa[s_me * SROW + col] = pre[r];
+            } else {
+                const int g = f - NACT;
+                const int col = g < NOUT ? D_OFF_O + g : (g < D_A1 ? D_OFF_A2 + (g - D_A2) : D_OFF_A1 + (g - D_A1));
+                sd[s_me * SROW + col] = pre[r];
             }
-            acc[r] += (double)s0 + (double)s1;
+        }
+        if (threadIdx.x < TILE) {
+            sa[s_me * SROW + A_OFF_ONE] = 1.0f;
+            sd[s_me * SROW + 5] = 0.0f;
+            sd[s_me * SROW + 6] = 0.0f;
+            sd[s_me * SROW + 7] = 0.0f;
+        }
+        __syncthreads();
+        if (tile + 1 < last) fetch(tile + 1);
+        if (busy) {
+            float f[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) f[q] = 0.0f;
+            for (int s = half; s < TILE; s += 2) {
+                const float4 d = *reinterpret_cast<const float4 *>(sd + s * SROW + K.doff);
+                const float4 v = *reinterpret_cast<const float4 *>(sa + s * SROW + K.aoff);
+                const float dd[4] = {d.x, d.y, d.z, d.w}, vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) f[4 * r + c] = fmaf(dd[r], vv[c], f[4 * r + c]);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += (double)f[q];
         }
     }
+    __syncthreads();
+    if (busy && half == 1)
 #pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-        const int e = threadIdx.x + r * TB;
-        if (e < NP) partial[(long long)blockIdx.x * NP + e] = acc[r];
+        for (int q = 0; q < 16; ++q) comb[id][q] = acc[q];
+    __syncthreads();
+    if (busy && half == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int e = task_param(K, r, c);
+                if (e >= 0) partial[(long long)blockIdx.x * NP + e] = acc[4 * r + c] + comb[id][4 * r + c];
+            }
     }
 }
 
-// grad[e] = sum_b partial[b][e]; loss sum of the window into *lsum (FP64)
+// grad[e] = sum_b partial[b][e] (64 entries per block, 4 stripes of partial rows combined in LDS);
+// block 0 also adds the window's loss into *lsum (FP64)
 __global__ __launch_bounds__(TB) void k_reduce(const double *partial, int nblk, const double *lossp, int nlb,
                                                double loss_scale, double *grad, double *lsum) {
-    const int e = blockIdx.x * TB + threadIdx.x;
-    if (e < NP) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partial[(long long)b * NP + e];
-        grad[e] = s;
-    }
+    __shared__ double st[4][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), stripe = threadIdx.x >> 6;
+    double s = 0.0;
+    if (e < NP)
+        for (int b = stripe; b < nblk; b += 4) s += partial[(long long)b * NP + e];
+    st[stripe][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (stripe == 0 && e < NP) grad[e] = st[0][threadIdx.x] + st[1][threadIdx.x] + st[2][threadIdx.x] + st[3][threadIdx.x];
     if (blockIdx.x == 0) {
+        __syncthreads();
         double l = 0.0;
         for (int b = threadIdx.x; b < nlb; b += TB) l += lossp[b];
         l = block_sum(l);
@@ -356,8 +431,8 @@ __global__ __launch_bounds__(TB) void k_reduce(const double *partial, int nblk, 
 }
 
 // Adam with bias correction (t counts from 1); FP64 master weights, FP32 copy
-__global__ __launch_bounds__(TB) void k_adam(double *w64, float *w32, double *m, double *v, const double *grad, double lr,
-                                             double c1, double c2) {
+__global__ __launch_bounds__(TB) void k_adam(double *w64, float *w32, float *wt, double *m, double *v, const double *grad,
+                                             double lr, double c1, double c2) {
     const int e = blockIdx.x * TB + threadIdx.x;
     if (e >= NP) return;
     const double g = grad[e];
@@ -369,11 +444,12 @@ __global__ __launch_bounds__(TB) void k_adam(double *w64, float *w32, double *m,
     const double wn = w64[e] - lr * (mn / c1) / (sqrt(vn / c2) + 1e-8);
     w64[e] = wn;
     w32[e] = (float)wn;
+    wt[closure_tpos(e)] = (float)wn;
 }
 
 // identity -> tanh: scale so that the tanh network equals the identity network to O(eps^2) in
 // its near-linear regime: W1, b1, b2 by eps (pre-activations shrink by eps), W3 by 1 / eps
-__global__ __launch_bounds__(TB) void k_embed(double *w64, float *w32, double eps) {
+__global__ __launch_bounds__(TB) void k_embed(double *w64, float *w32, float *wt, double eps) {
     const int e = blockIdx.x * TB + threadIdx.x;
     if (e >= NP) return;
     double f = 1.0;
@@ -382,11 +458,15 @@ __global__ __launch_bounds__(TB) void k_embed(double *w64, float *w32, double ep
     const double wn = w64[e] * f;
     w64[e] = wn;
     w32[e] = (float)wn;
+    wt[closure_tpos(e)] = (float)wn;
 }
 
-__global__ __launch_bounds__(TB) void k_to_f32(const double *w64, float *w32) {
+__global__ __launch_bounds__(TB) void k_to_f32(const double *w64, float *w32, float *wt) {
     const int e = blockIdx.x * TB + threadIdx.x;
-    if (e < NP) w32[e] = (float)w64[e];
+    if (e < NP) {
+        w32[e] = (float)w64[e];
+        wt[closure_tpos(e)] = (float)w64[e];
+    }
 }
 
 __global__ void k_fill4(float4 *p, long long n) {
@@ -456,6 +536,7 @@ struct fdtdb_trainer_s {
     double *w64 = nullptr, *m = nullptr, *v = nullptr;
     double *snap = nullptr;                 // weights, m, v before the current epoch
     float *w32 = nullptr;
+    float *wt = nullptr;                    // FP32 weights in the transposed layout (forward pass)
     long long adam_t = 0;
     bool loaded = false, have_w = false;
 
@@ -482,10 +563,10 @@ fdtdb_status window_grad(fdtdb_trainer_s *t, long long c, double loss_scale) {
     const int W = t->W;
     const unsigned nb = nblk(N);
     if (t->act == 0)
-        hipLaunchKernelGGL(k_forward<0>, dim3(nb), dim3(TB), 0, t->stream, t->X, t->Y, t->w32, t->h, t->act_buf, t->res,
+        hipLaunchKernelGGL(k_forward<0>, dim3(nb), dim3(TB), 0, t->stream, t->X, t->Y, t->wt, t->h, t->act_buf, t->res,
                            t->lossp, N, W, c * W);
     else
-        hipLaunchKernelGGL(k_forward<1>, dim3(nb), dim3(TB), 0, t->stream, t->X, t->Y, t->w32, t->h, t->act_buf, t->res,
+        hipLaunchKernelGGL(k_forward<1>, dim3(nb), dim3(TB), 0, t->stream, t->X, t->Y, t->wt, t->h, t->act_buf, t->res,
                            t->lossp, N, W, c * W);
     THIP(hipGetLastError());
     const float scale = (float)(2.0 / ((double)N * W));
@@ -497,7 +578,7 @@ fdtdb_status window_grad(fdtdb_trainer_s *t, long long c, double loss_scale) {
     hipLaunchKernelGGL(k_wgrad, dim3(t->wg_blocks), dim3(TB), 0, t->stream, t->act_buf, t->del, N, W, t->wg_tiles,
                        t->partial);
     THIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->partial, t->wg_blocks, t->lossp, (int)nb,
+    hipLaunchKernelGGL(k_reduce, dim3((NP + 63) / 64), dim3(TB), 0, t->stream, t->partial, t->wg_blocks, t->lossp, (int)nb,
                        loss_scale / ((double)N * W), t->grad, t->lsum);
     THIP(hipGetLastError());
     return FDTDB_OK;
@@ -550,7 +631,7 @@ fdtdb_status fdtdb_trainer_create(const fdtdb_trainer_desc *d, fdtdb_trainer *ou
     A((void **)&t->h, 16 * (size_t)N);
     A((void **)&t->lossp, 8 * (size_t)nblk(N));
     const long long ntiles = ((N + TILE - 1) / TILE) * W;
-    t->wg_tiles = (int)std::max<long long>(1, (ntiles + 2047) / 2048);
+    t->wg_tiles = (int)std::max<long long>(1, (ntiles + 1023) / 1024);
     t->wg_blocks = (int)((ntiles + t->wg_tiles - 1) / t->wg_tiles);
     A((void **)&t->partial, 8 * (size_t)NP * t->wg_blocks);
     A((void **)&t->grad, 8 * (size_t)NP);
@@ -559,6 +640,7 @@ fdtdb_status fdtdb_trainer_create(const fdtdb_trainer_desc *d, fdtdb_trainer *ou
     A((void **)&t->m, 8 * (size_t)NP);
     A((void **)&t->v, 8 * (size_t)NP);
     A((void **)&t->w32, 4 * (size_t)NP);
+    A((void **)&t->wt, 4 * (size_t)NP);
     A((void **)&t->snap, 48 * (size_t)NP);
     if (st != FDTDB_OK) { fdtdb_trainer_destroy(t); return st; }
     hipError_t e = hipMemcpy(t->coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice);
@@ -626,6 +708,9 @@ fdtdb_status fdtdb_trainer_set_weights(fdtdb_trainer t, const float *w) {
     THIP(hipStreamSynchronize(t->stream));
     THIP(hipMemcpy(t->w64, w64.data(), 8 * (size_t)NP, hipMemcpyHostToDevice));
     THIP(hipMemcpy(t->w32, w, 4 * (size_t)NP, hipMemcpyHostToDevice));
+    std::vector<float> wt(NP);
+    for (int e = 0; e < NP; e++) wt[closure_tpos(e)] = w[e];
+    THIP(hipMemcpy(t->wt, wt.data(), 4 * (size_t)NP, hipMemcpyHostToDevice));
     TTRY(zero(t, t->m, NP));
     TTRY(zero(t, t->v, NP));
     THIP(hipStreamSynchronize(t->stream));
@@ -646,7 +731,7 @@ fdtdb_status fdtdb_trainer_set_activation(fdtdb_trainer t, int activation, doubl
     if (!t || (activation != 0 && activation != 1)) return tfail(FDTDB_E_INVALID, "bad argument");
     if (activation == 0 && t->act == 1 && t->have_w) {
         if (!(eps > 0.0) || !(eps <= 1.0)) return tfail(FDTDB_E_INVALID, "eps must be in (0, 1]");
-        hipLaunchKernelGGL(k_embed, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32, eps);
+        hipLaunchKernelGGL(k_embed, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32, t->wt, eps);
         THIP(hipGetLastError());
         TTRY(zero(t, t->m, NP));
         TTRY(zero(t, t->v, NP));
@@ -701,7 +786,7 @@ fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double 
             TTRY(window_grad(t, c, 1.0 / (double)nwin));
             t->adam_t++;
             const double c1 = 1.0 - std::pow(0.9, (double)t->adam_t), c2 = 1.0 - std::pow(0.999, (double)t->adam_t);
-            hipLaunchKernelGGL(k_adam, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32, t->m, t->v, t->grad, rate,
+            hipLaunchKernelGGL(k_adam, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32, t->wt, t->m, t->v, t->grad, rate,
                                c1, c2);
             THIP(hipGetLastError());
         }
@@ -717,7 +802,7 @@ fdtdb_status fdtdb_trainer_train(fdtdb_trainer t, int epochs, double lr, double 
             THIP(hipMemcpyAsync(t->w64, sb, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
             THIP(hipMemcpyAsync(t->m, sb + NP, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
             THIP(hipMemcpyAsync(t->v, sb + 2 * NP, 8 * (size_t)NP, hipMemcpyDeviceToDevice, t->stream));
-            hipLaunchKernelGGL(k_to_f32, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32);
+            hipLaunchKernelGGL(k_to_f32, dim3(nblk(NP)), dim3(TB), 0, t->stream, t->w64, t->w32, t->wt);
             THIP(hipGetLastError());
             t->adam_t = t_snap[back];
             rate = 0.5 * rate_snap[back];
