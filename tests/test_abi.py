@@ -75,3 +75,59 @@ def test_product_never_imports_oracle():
                     txt = open(os.path.join(dirpath, f)).read()
                     assert "import oracle" not in txt and "from oracle" not in txt, f
                     assert "fdtd_oracle" not in txt, f
+
+
+def _desc(ndim=3, n=(8, 8, 8), courant=0.5, dtype=0):
+    from paper_2505_23963_amd.fdtdb import GridDesc
+    d = GridDesc()
+    d.ndim = ndim
+    for a in range(3):
+        d.n[a] = n[a]
+        d.bc[a] = 1
+        d.pml_cells[a] = 0
+    d.courant = courant
+    d.dtype = dtype
+    d.pml_R0 = 1e-8
+    return d
+
+
+@pytest.mark.parametrize("kw, code", [
+    (dict(ndim=0), -1), (dict(ndim=4), -1),                         # dimensionality
+    (dict(courant=0.0), -1), (dict(courant=0.6), -4),                # 3D vacuum limit 1/sqrt(3)
+    (dict(n=(0, 8, 8)), -1),                                         # empty axis
+    (dict(n=(2048, 2048, 1024)), -1),                                # beyond 32-bit cell indexing
+    (dict(dtype=7), -1),
+])
+def test_create_grid_rejects_bad_descriptors_before_touching_the_device(libfdtdb, kw, code):
+    """Argument checks run on the host before any HIP call, so they are exercised without a GPU."""
+    from paper_2505_23963_amd import lib
+    L = lib()
+    h = ctypes.c_void_p()
+    assert L.fdtdb_create_grid(ctypes.byref(_desc(**kw)), ctypes.byref(h)) == code
+    assert not h.value
+    assert L.fdtdb_last_error()
+
+
+def test_trainer_and_batch_reject_bad_descriptors(libfdtdb):
+    from paper_2505_23963_amd import lib
+    from paper_2505_23963_amd.fdtdb import TrainerDesc
+    L = lib()
+    w = np.array([1.0]); g = np.array([0.01]); k = np.array([0.1])
+    P = ctypes.POINTER(ctypes.c_double)
+
+    def desc(**kw):
+        d = TrainerDesc()
+        d.ntraj, d.nsteps, d.window, d.activation, d.dt, d.n_bath = 4, 128, 64, 0, 0.5, 1
+        d.omega_j, d.gamma_j, d.k_j = (a.ctypes.data_as(P) for a in (w, g, k))
+        for key, v in kw.items():
+            setattr(d, key, v)
+        return d
+
+    h = ctypes.c_void_p()
+    for bad in (dict(nsteps=100), dict(window=0), dict(window=5000, nsteps=5000), dict(activation=2), dict(dt=0.0),
+                dict(n_bath=0), dict(ntraj=0)):
+        assert L.fdtdb_trainer_create(ctypes.byref(desc(**bad)), ctypes.byref(h)) == -1, bad
+        assert not h.value
+    lens = (ctypes.c_int64 * 2)(100, 0)
+    assert L.fdtdb_batch_create(2, lens, 0, 0.5, 8, 1e-8, None, ctypes.byref(h)) == -1     # empty cavity
+    assert L.fdtdb_batch_create(0, lens, 0, 0.5, 8, 1e-8, None, ctypes.byref(h)) == -1     # no cavities
