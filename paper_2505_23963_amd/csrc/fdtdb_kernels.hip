@@ -752,6 +752,127 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// 2D TM (E_z, H_x, H_y) background E and H updates, four y-consecutive cells per thread (y is the
+// fastest axis of a 2D grid), regions from the launch's table, CPML psi in the same pass.
+// ---------------------------------------------------------------------------------------------
+template <class A>
+__device__ __forceinline__ const RegionDesc &v4_region2(const A &a, Cell4 &c) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    int r = -1;
+#pragma unroll
+    for (int s = 0; s < kMaxGroup; ++s) r += b >= a.rd->block0[s];
+    const RegionDesc &D = a.rd->d[r];
+    const int t = (b - a.rd->block0[r]) * kBlock + threadIdx.x;
+    const int ext1q = D.ext[1] >> 2;
+    c.live = t < D.ext[0] * ext1q;
+    const int ii = t / ext1q;
+    c.i = D.lo[0] + ii;
+    c.j = D.lo[1] + 4 * (t - ii * ext1q);
+    c.k = 0;
+    c.tc = 4 * t;
+    return D;
+}
+
+// CPML of one curl term for 4 y-consecutive cells (coefficients by axis position)
+template <typename T>
+__device__ __forceinline__ void cpml4y(void *psi, int tc, int ax, int i, int j, const double *pb, const double *pc,
+                                       double *term) {
+    using V = vec4_t<T>;
+    V *pp = reinterpret_cast<V *>(static_cast<T *>(psi) + tc);
+    const V p = *pp;
+    double o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int x = ax == 0 ? i : j + e;
+        o[e] = pb[x] * lane4<T>(p, e) + pc[x] * term[e];
+        term[e] += o[e];
+    }
+    V w;
+    w.x = (T)o[0]; w.y = (T)o[1]; w.z = (T)o[2]; w.w = (T)o[3];
+    *pp = w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_e2_v4(const EArgs a) {
+    using V = vec4_t<T>;
+    Cell4 C;
+    const RegionDesc &D = v4_region2(a, C);
+    if (!C.live) return;
+    const int i = C.i, j = C.j;
+    const int s0 = a.n[1];
+    const int q = i * s0 + j;
+    const T *Hx = static_cast<const T *>(a.H[0]);
+    const T *Hy = static_cast<const T *>(a.H[1]);
+    const bool okx = i > 0 || a.per[0], oky = j > 0 || a.per[1];
+    const int qx = i > 0 ? q - s0 : (a.per[0] ? q + (a.n[0] - 1) * s0 : q);
+    const int qy = j > 0 ? q - 1 : (a.per[1] ? q + a.n[1] - 1 : q);
+    const V hx = *reinterpret_cast<const V *>(Hx + q);
+    const V hy = *reinterpret_cast<const V *>(Hy + q);
+    const V hy_x = *reinterpret_cast<const V *>(Hy + qx);
+    const double hx_y = oky ? (double)Hx[qy] : 0.0;
+    V *Ez = reinterpret_cast<V *>(static_cast<T *>(a.E[2]) + q);
+    const V ez = *Ez;
+    // Ez: t1 = d_x Hy, t2 = d_y Hx
+    double t1[4], t2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double hxe = lane4<T>(hx, e), hye = lane4<T>(hy, e);
+        t1[e] = hye - (okx ? lane4<T>(hy_x, e) : 0.0);
+        t2[e] = hxe - (e > 0 ? lane4<T>(hx, e - 1) : hx_y);
+    }
+    if (D.psi[2][0]) cpml4y<T>(D.psi[2][0], C.tc, 0, i, j, a.pml_b[0], a.pml_c[0], t1);
+    if (D.psi[2][1]) cpml4y<T>(D.psi[2][1], C.tc, 1, i, j, a.pml_b[1], a.pml_c[1], t2);
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    const double ce = a.dt * D.inv_eps;
+    double o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = lane4<T>(ez, e) + ce * (t1[e] - t2[e]) - source_term(a, amp, 2, i, j + e, 0);
+    V w;
+    w.x = (T)o[0]; w.y = (T)o[1]; w.z = (T)o[2]; w.w = (T)o[3];
+    *Ez = w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_h2_v4(const HArgs a) {
+    using V = vec4_t<T>;
+    Cell4 C;
+    const RegionDesc &D = v4_region2(a, C);
+    if (!C.live) return;
+    const int i = C.i, j = C.j;
+    const int s0 = a.n[1];
+    const int q = i * s0 + j;
+    const T *Ez = static_cast<const T *>(a.E[2]);
+    const bool okx = i < a.n[0] - 1 || a.per[0], oky = j + 4 < a.n[1] || a.per[1];
+    const int qx = i < a.n[0] - 1 ? q + s0 : (a.per[0] ? q - (a.n[0] - 1) * s0 : q);
+    const int qy = j + 4 < a.n[1] ? q + 4 : (a.per[1] ? q + 4 - a.n[1] : q);
+    const V ez = *reinterpret_cast<const V *>(Ez + q);
+    const V ez_x = *reinterpret_cast<const V *>(Ez + qx);
+    const double ez_y = oky ? (double)Ez[qy] : 0.0;
+    V *Hx = reinterpret_cast<V *>(static_cast<T *>(a.H[0]) + q);
+    V *Hy = reinterpret_cast<V *>(static_cast<T *>(a.H[1]) + q);
+    const V hx = *Hx, hy = *Hy;
+    // Hx: t1 = d_y Ez (axis y); Hy: t2 = d_x Ez (axis x), H_y <- H_y + dt t2
+    double tx[4], ty[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double eze = lane4<T>(ez, e);
+        tx[e] = (e < 3 ? lane4<T>(ez, e + 1) : ez_y) - eze;
+        ty[e] = (okx ? lane4<T>(ez_x, e) : 0.0) - eze;
+    }
+    if (D.psi[0][0]) cpml4y<T>(D.psi[0][0], C.tc, 1, i, j, a.pml_b[1], a.pml_c[1], tx);
+    if (D.psi[1][1]) cpml4y<T>(D.psi[1][1], C.tc, 0, i, j, a.pml_b[0], a.pml_c[0], ty);
+    const double dt = a.dt;
+    V wx, wy;
+    wx.x = (T)(lane4<T>(hx, 0) - dt * tx[0]); wx.y = (T)(lane4<T>(hx, 1) - dt * tx[1]);
+    wx.z = (T)(lane4<T>(hx, 2) - dt * tx[2]); wx.w = (T)(lane4<T>(hx, 3) - dt * tx[3]);
+    wy.x = (T)(lane4<T>(hy, 0) + dt * ty[0]); wy.y = (T)(lane4<T>(hy, 1) + dt * ty[1]);
+    wy.z = (T)(lane4<T>(hy, 2) + dt * ty[2]); wy.w = (T)(lane4<T>(hy, 3) + dt * ty[3]);
+    *Hx = wx;
+    *Hy = wy;
+}
+
+// ---------------------------------------------------------------------------------------------
 // 3D E update of background regions (vacuum, dielectric, CPML) or of a Drude region (DRUDE:
 // the polarization increment V = P^{n+1/2} - P^{n-1/2} read and written in the same pass), four
 // z-consecutive cells per thread, regions from the launch's table (no energy sampling: launches
@@ -1025,6 +1146,12 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
 
 template <int DIM, typename T>
 static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int ng, bool pml, bool energy, hipStream_t s) {
+    if (DIM == 2 && kind == K_BACKGROUND && a.nrd < 0) {   // y-vectorized 2D launch over the table's regions
+        const long long n = (long long)a.ext[0] * a.ext12;
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_update_e2_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     if (DIM == 3 && (kind == K_BACKGROUND || kind == K_DRUDE) && a.nrd < 0) {   // z-vectorized launch
         const long long n = (long long)a.ext[0] * a.ext12;
         if (n == 0) return hipSuccess;
@@ -1093,6 +1220,10 @@ static hipError_t launch_h_dim(const HArgs &a, bool pml, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (DIM == 3 && a.nrd < 0) {       // z-vectorized launch: the table holds the regions, ext[0] the threads
         hipLaunchKernelGGL(k_update_h3_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    if (DIM == 2 && a.nrd < 0) {       // y-vectorized 2D launch
+        hipLaunchKernelGGL(k_update_h2_v4<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
     if (pml)

@@ -474,8 +474,9 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
             s += n;
         }
     };
-    // 3D regions whose z range is 4-aligned take the z-vectorized kernels
+    // regions whose fastest-axis range (3D: z, 2D: y) is 4-aligned take the vectorized kernels
     auto z4 = [&](const Region &rg) {
+        if (g->ndim == 2) return rg.lo[1] % 4 == 0 && (rg.hi[1] - rg.lo[1]) % 4 == 0 && g->n[1] % 4 == 0;
         return g->ndim == 3 && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 && g->n[2] % 4 == 0;
     };
     {
@@ -485,7 +486,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
             if (rg.mat >= 0) {
                 const Material &mt = g->mats[rg.mat];
                 const bool m4 = mt.mext[2] % 4 == 0 && (rg.lo[2] - (int)mt.lo[2]) % 4 == 0;
-                (mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy ? drude4 : solo).push_back(i);
+                (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy ? drude4 : solo).push_back(i);
             } else if (z4(rg) && !rg.energy) {
                 bg4.push_back(i);
             } else {
