@@ -181,16 +181,23 @@ __device__ __forceinline__ void unflatten(int t, const int *lo, const int *ext, 
 // E / polarization update of a Lorentz-Bath material whose bath force comes from the learned
 // closure.  Per E component and cell: x = [E s_E, P s_P, V s_V, h] -> tanh(W1 x + b1) ->
 // tanh(W2 z1 + b2) -> o = W3 z2 + b3; h += o[0:4]; the bath force term of eq:Pz_update-LB is
-// o[4] / s_S.  Layers 1 and 3 run on the vector ALU with the weights read through the constant
-// address space; layer 2 (32 x 32, three quarters of the work) runs on the matrix cores as FP32
-// MFMA 16x16x4 over tiles of 16 cells: each wave stages its 64 cells' z1 rows in LDS, reads them
-// back in the B-operand layout (lane l: cell l mod 16 of the tile, feature 4 s + l / 16 at step s),
-// holds W2 as the A operand in registers, and writes z2 back over the tile's rows, from where each
-// lane reads its own cell's row for layer 3.  Every lane of a wave takes part (lanes past the end
+// o[4] / s_S.  Layers 1 and 2 run on the matrix cores as FP32 MFMA 16x16x4 over tiles of 16 cells:
+// each wave stages its 64 cells' inputs in LDS, reads them back in the B-operand layout (lane l:
+// cell l mod 16 of the tile, feature 4 s + l / 16 at step s), holds W1 and W2 as A operands in
+// registers, and writes each layer's output back over the tile's rows; layer 3 (5 outputs) runs on
+// the vector ALU on each lane's own row with the weights read through the constant address space.  Every lane of a wave takes part (lanes past the end
 // of the region compute on a clamped cell and store nothing).
 // ---------------------------------------------------------------------------------------------
 typedef float f4v __attribute__((ext_vector_type(4)));
-constexpr int kClRow = 36;    // LDS row stride (floats): 16 rows x 4 groups of B reads hit 64 banks once
+constexpr int kClRow = 36;
+
+// Each wave of the closure kernel stages through its own LDS rows only, so a wave-level barrier with
+// an LDS fence orders its writes and reads (no block-wide barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}    // LDS row stride (floats): 16 rows x 4 groups of B reads hit 64 banks once
 
 template <int DIM, typename T, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
@@ -202,21 +209,27 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
     const bool live = t0 < ncell;
     const int t = live ? t0 : ncell - 1;
     constexpr int W = kClosureWidth;
-    // layers 1 and 3 read the transposed copy (one contiguous row per input feature)
+    // layer 3 reads the transposed copy (one contiguous row per input feature)
     const cfptr wt = (cfptr)(a.cw + kClosureParams);
-    const cfptr W1T = wt, b1 = W1T + W * 7, W3T = b1 + W + W * W + W, b3 = W3T + 5 * W;
+    const cfptr W3T = wt + W * 7 + W + W * W + W, b3 = W3T + 5 * W;
     // layer-2 operands of this lane: A = W2 rows 16 h + (lane mod 16), columns 4 s + lane / 16;
     // accumulator start = b2 of units 16 h + 4 (lane / 16) + v
-    const float *W2 = a.cw + W * 7 + W;
+    const float *W1 = a.cw, *b1v = W1 + W * 7;
+    const float *W2 = b1v + W;
     const float *b2 = W2 + W * W;
-    float wa[2][8];
-    f4v bias2[2];
+    float wa[2][8], wa1[2][2];
+    f4v bias1[2], bias2[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) wa[h][s] = W2[(16 * h + jl) * W + 4 * s + g];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) bias2[h][v] = b2[16 * h + 4 * g + v];
+        for (int s = 0; s < 2; ++s) wa1[h][s] = 4 * s + g < 7 ? W1[(16 * h + jl) * 7 + 4 * s + g] : 0.0f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            bias1[h][v] = b1v[16 * h + 4 * g + v];
+            bias2[h][v] = b2[16 * h + 4 * g + v];
+        }
     }
     double ef = 0.0, ep = 0.0;
     bool sample = false;
@@ -256,26 +269,29 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
         float4 hv = *hp;
         const float x[7] = {(float)(En * a.cscale[0]), (float)(Pc * a.cscale[1]),
                             (float)((Pc - Pp) / a.dt * a.cscale[2]), hv.x, hv.y, hv.z, hv.w};
-        // layer 1 (vector ALU), z1 row to LDS
-        float z1[W];
-#pragma unroll
-        for (int u = 0; u < W; ++u) z1[u] = b1[u];
-#pragma unroll
-        for (int v = 0; v < 7; ++v) {
-#pragma unroll
-            for (int u = 0; u < W; ++u) z1[u] = fmaf(W1T[v * W + u], x[v], z1[u]);
-            __asm__ volatile("" ::: "memory");
-        }
-        tanh_n<W>(z1);
-#pragma unroll
-        for (int u = 0; u < W; u += 4)
-            *reinterpret_cast<float4 *>(row + lane * kClRow + u) = make_float4(z1[u], z1[u + 1], z1[u + 2], z1[u + 3]);
-        __syncthreads();
-        // layer 2 (matrix cores), tile by tile; z2 overwrites the tile's rows
+        // x row to LDS (7 inputs and a zero); then per tile of 16 cells: layer 1 (K = 8) and layer 2
+        // (K = 32) on the matrix cores, z1 and then z2 written over the tile's rows
+        *reinterpret_cast<float4 *>(row + lane * kClRow) = make_float4(x[0], x[1], x[2], x[3]);
+        *reinterpret_cast<float4 *>(row + lane * kClRow + 4) = make_float4(x[4], x[5], x[6], 0.0f);
+        wave_sync();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            f4v acc0 = bias2[0], acc1 = bias2[1];
             const float *src = row + (16 * r + jl) * kClRow + g;
+            float *dst = row + (16 * r + jl) * kClRow + 4 * g;
+            f4v c0 = bias1[0], c1 = bias1[1];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const float bv = src[4 * s];
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa1[0][s], bv, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa1[1][s], bv, c1, 0, 0, 0);
+            }
+            float z1[8] = {c0[0], c0[1], c0[2], c0[3], c1[0], c1[1], c1[2], c1[3]};
+            tanh_n<8>(z1);
+            wave_sync();      // the tile's x rows are consumed
+            *reinterpret_cast<float4 *>(dst) = make_float4(z1[0], z1[1], z1[2], z1[3]);
+            *reinterpret_cast<float4 *>(dst + 16) = make_float4(z1[4], z1[5], z1[6], z1[7]);
+            wave_sync();
+            f4v acc0 = bias2[0], acc1 = bias2[1];
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const float bv = src[4 * s];
@@ -284,11 +300,11 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
             }
             float zz[8] = {acc0[0], acc0[1], acc0[2], acc0[3], acc1[0], acc1[1], acc1[2], acc1[3]};
             tanh_n<8>(zz);
-            float *dst = row + (16 * r + jl) * kClRow + 4 * g;
+            wave_sync();      // the tile's z1 rows are consumed
             *reinterpret_cast<float4 *>(dst) = make_float4(zz[0], zz[1], zz[2], zz[3]);
             *reinterpret_cast<float4 *>(dst + 16) = make_float4(zz[4], zz[5], zz[6], zz[7]);
         }
-        __syncthreads();
+        wave_sync();
         // layer 3 (vector ALU) on this lane's own row
         float z2[W];
 #pragma unroll
@@ -296,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
             const float4 v4 = *reinterpret_cast<const float4 *>(row + lane * kClRow + u);
             z2[u] = v4.x; z2[u + 1] = v4.y; z2[u + 2] = v4.z; z2[u + 3] = v4.w;
         }
-        __syncthreads();
+        wave_sync();
         float o[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) o[q] = b3[q];
