@@ -139,7 +139,6 @@ __global__ __launch_bounds__(NT) void k_batch1d(const Args a, const int nsteps, 
     const double dt = a.dt;
     const double ie = a.cav[cav].inv_eps[ty];   // indexed in global memory (a runtime index into a
                                                  // private copy would live in scratch)
-    double dftE = 0.0;
     for (int s = 0; s < nsteps; ++s) {
         const int n = step0 + s;
         cdptr cf = cf0;
@@ -148,6 +147,8 @@ __global__ __launch_bounds__(NT) void k_batch1d(const Args a, const int nsteps, 
         sH[t] = H;
         __syncthreads();
         const double Hm = t > 0 ? sH[t - 1] : 0.0;        // segment edge: wall or invalid halo
+        // the previous step's DFT sample of H: the mean over the node and its left neighbour
+        if (s > 0 && cv.dft_x >= 0 && x == cv.dft_x && own) stage[1][s - 1] = 0.5 * (Hm + H);
         double Eo = E, En = E;
         double en_f = 0.0, en_p = 0.0, en_b = 0.0;
         const bool sample = cv.en_every > 0 && (n % cv.en_every) == 0;
@@ -254,16 +255,14 @@ __global__ __launch_bounds__(NT) void k_batch1d(const Args a, const int nsteps, 
             }
             H = (double)(T)(H + dt * t2);
         }
-        // ---- DFT samples: E at the monitor node, H averaged over the two adjacent nodes
-        if (cv.dft_x >= 0 && x == cv.dft_x && own) dftE = E;
-        sH[t] = H;
-        __syncthreads();
-        if (cv.dft_x >= 0 && x == cv.dft_x && own) {
-            stage[0][s] = dftE;
-            stage[1][s] = 0.5 * (sH[t - 1] + H);
-        }
-        __syncthreads();
+        // ---- DFT sample of E at the monitor node (H is sampled at the start of the next step)
+        if (cv.dft_x >= 0 && x == cv.dft_x && own) stage[0][s] = E;
     }
+    // the last step's H sample, then every sample is visible to the block
+    sH[t] = H;
+    __syncthreads();
+    if (cv.dft_x >= 0 && x == cv.dft_x && own) stage[1][nsteps - 1] = 0.5 * ((t > 0 ? sH[t - 1] : 0.0) + H);
+    __syncthreads();
     // ---- write the owned cells back
     if (inside && own) {
         T *Eo = static_cast<T *>(a.E), *Ho = static_cast<T *>(a.H);
