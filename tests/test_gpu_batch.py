@@ -87,3 +87,49 @@ def test_batch_full_workload_short(oracle_lib):
     for c in (7, 50):
         o = oracle_lib.run(ps[c], steps=400)
         assert rel(b.field(c, 2), o.field(2)[:, 0, 0]) < 1e-5, c
+
+
+def _fit_rate(trace, every, dt, t_lo, t_hi):
+    """Least-squares fit of E_bath(t) = E_inf (1 - exp(-G t)) on [t_lo, t_hi]: for each G the best E_inf is
+    linear, G by a coarse scan and golden-section refinement."""
+    t = np.arange(len(trace)) * every * dt
+    sel = (t >= t_lo) & (t <= t_hi)
+    t, y = t[sel], trace[sel]
+
+    def resid(G):
+        f = 1.0 - np.exp(-G * t)
+        e = (f @ y) / (f @ f)
+        return np.sum((y - e * f) ** 2)
+
+    grid = np.geomspace(1e-5, 1.0, 400)
+    k = int(np.argmin([resid(G) for G in grid]))
+    a, b = grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)]
+    phi = (np.sqrt(5.0) - 1.0) / 2.0
+    for _ in range(80):
+        c, d = b - phi * (b - a), a + phi * (b - a)
+        if resid(c) < resid(d):
+            b = d
+        else:
+            a = c
+    return 0.5 * (a + b)
+
+
+def test_batch_relaxation_rates_match_oracle(oracle_lib):
+    """Relaxation rates fitted to the bath-energy growth (FP32 batched path vs FP64 oracle, same fit on
+    [2 t0, pi / dw], before the discrete bath revives)."""
+    from paper_2505_23963_amd import Batch
+    ps = cavities(4, 600, "f32", lengths=[1500, 1900, 2400, 3100])
+    b = Batch(ps, tiling=(32, 512))
+    b.step(600)
+    b.synchronize()
+    for c, p in enumerate(ps):
+        o = oracle_lib.run(p, steps=600)
+        eg, eo = b.energy(c)[:, 2], o.energy(0)[:, 2]
+        m = p.materials[1]
+        dw = 0.4 / (m.n_bath - 1)
+        t0 = 5.0 / p.sources[0].width
+        every = p.energies[0].every
+        Gg = _fit_rate(eg, every, p.courant, 2 * t0, np.pi / dw)
+        Go = _fit_rate(eo, every, p.courant, 2 * t0, np.pi / dw)
+        print(f"[gpu] cavity {c}: rate {Gg:.6e} (GPU) vs {Go:.6e} (oracle)", flush=True)
+        assert Go > 0 and abs(Gg - Go) <= 1e-4 * Go, (c, Gg, Go)
