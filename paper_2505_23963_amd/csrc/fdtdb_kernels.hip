@@ -731,10 +731,17 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     const V ez_x = *reinterpret_cast<const V *>(Ez + qx);
     const double ex_z = okz ? (double)Ex[qz] : 0.0;
     const double ey_z = okz ? (double)Ey[qz] : 0.0;
-    V *Hx = reinterpret_cast<V *>(static_cast<T *>(a.H[0]) + q);
-    V *Hy = reinterpret_cast<V *>(static_cast<T *>(a.H[1]) + q);
-    V *Hz = reinterpret_cast<V *>(static_cast<T *>(a.H[2]) + q);
-    const V hx = *Hx, hy = *Hy, hz = *Hz;
+    // H is read once and written once per step: streamed (non-temporal); E rows are shared with the
+    // neighbouring threads and stay cacheable
+    using NV = nvec4_t<T>;
+    NV *Hx = reinterpret_cast<NV *>(static_cast<T *>(a.H[0]) + q);
+    NV *Hy = reinterpret_cast<NV *>(static_cast<T *>(a.H[1]) + q);
+    NV *Hz = reinterpret_cast<NV *>(static_cast<T *>(a.H[2]) + q);
+    const NV hxn = __builtin_nontemporal_load(Hx), hyn = __builtin_nontemporal_load(Hy), hzn = __builtin_nontemporal_load(Hz);
+    V hx, hy, hz;
+    hx.x = hxn[0]; hx.y = hxn[1]; hx.z = hxn[2]; hx.w = hxn[3];
+    hy.x = hyn[0]; hy.y = hyn[1]; hy.z = hyn[2]; hy.w = hyn[3];
+    hz.x = hzn[0]; hz.y = hzn[1]; hz.z = hzn[2]; hz.w = hzn[3];
     const double dt = a.dt;
     // curl terms per component: t1 along axis a1, t2 along axis a2 (Hx: y, z; Hy: z, x; Hz: x, y)
     double tx1[4], tx2[4], ty1[4], ty2[4], tz1[4], tz2[4];
@@ -762,9 +769,13 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     wy.z = (T)(lane4<T>(hy, 2) - dt * (ty1[2] - ty2[2])); wy.w = (T)(lane4<T>(hy, 3) - dt * (ty1[3] - ty2[3]));
     wz.x = (T)(lane4<T>(hz, 0) - dt * (tz1[0] - tz2[0])); wz.y = (T)(lane4<T>(hz, 1) - dt * (tz1[1] - tz2[1]));
     wz.z = (T)(lane4<T>(hz, 2) - dt * (tz1[2] - tz2[2])); wz.w = (T)(lane4<T>(hz, 3) - dt * (tz1[3] - tz2[3]));
-    *Hx = wx;
-    *Hy = wy;
-    *Hz = wz;
+    NV ox, oy, oz;
+    ox[0] = wx.x; ox[1] = wx.y; ox[2] = wx.z; ox[3] = wx.w;
+    oy[0] = wy.x; oy[1] = wy.y; oy[2] = wy.z; oy[3] = wy.w;
+    oz[0] = wz.x; oz[1] = wz.y; oz[2] = wz.z; oz[3] = wz.w;
+    __builtin_nontemporal_store(ox, Hx);
+    __builtin_nontemporal_store(oy, Hy);
+    __builtin_nontemporal_store(oz, Hz);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -919,10 +930,17 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     const V hz_x = *reinterpret_cast<const V *>(Hz + qx);
     const double hx_z = okz ? (double)Hx[qz] : 0.0;
     const double hy_z = okz ? (double)Hy[qz] : 0.0;
-    V *Ex = reinterpret_cast<V *>(static_cast<T *>(a.E[0]) + q);
-    V *Ey = reinterpret_cast<V *>(static_cast<T *>(a.E[1]) + q);
-    V *Ez = reinterpret_cast<V *>(static_cast<T *>(a.E[2]) + q);
-    const V ex = *Ex, ey = *Ey, ez = *Ez;
+    // E is read once and written once per step: streamed (non-temporal); H rows are shared with the
+    // neighbouring threads and stay cacheable
+    using NV = nvec4_t<T>;
+    NV *Ex = reinterpret_cast<NV *>(static_cast<T *>(a.E[0]) + q);
+    NV *Ey = reinterpret_cast<NV *>(static_cast<T *>(a.E[1]) + q);
+    NV *Ez = reinterpret_cast<NV *>(static_cast<T *>(a.E[2]) + q);
+    const NV exn = __builtin_nontemporal_load(Ex), eyn = __builtin_nontemporal_load(Ey), ezn = __builtin_nontemporal_load(Ez);
+    V ex, ey, ez;
+    ex.x = exn[0]; ex.y = exn[1]; ex.z = exn[2]; ex.w = exn[3];
+    ey.x = eyn[0]; ey.y = eyn[1]; ey.z = eyn[2]; ey.w = eyn[3];
+    ez.x = ezn[0]; ez.y = ezn[1]; ez.z = ezn[2]; ez.w = ezn[3];
     // Ex: t1 = d_y Hz, t2 = d_z Hy;  Ey: t1 = d_z Hx, t2 = d_x Hz;  Ez: t1 = d_x Hy, t2 = d_y Hx
     double tx1[4], tx2[4], ty1[4], ty2[4], tz1[4], tz2[4];
 #pragma unroll
@@ -977,13 +995,16 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
             oz[e] = lane4<T>(ez, e) + ce * (tz1[e] - tz2[e]) - source_term(a, amp, 2, i, j, k + e);
         }
     }
-    V wx, wy, wz;
-    wx.x = (T)ox[0]; wx.y = (T)ox[1]; wx.z = (T)ox[2]; wx.w = (T)ox[3];
-    wy.x = (T)oy[0]; wy.y = (T)oy[1]; wy.z = (T)oy[2]; wy.w = (T)oy[3];
-    wz.x = (T)oz[0]; wz.y = (T)oz[1]; wz.z = (T)oz[2]; wz.w = (T)oz[3];
-    *Ex = wx;
-    *Ey = wy;
-    *Ez = wz;
+    NV wx, wy, wz;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        wx[e] = (T)ox[e];
+        wy[e] = (T)oy[e];
+        wz[e] = (T)oz[e];
+    }
+    __builtin_nontemporal_store(wx, Ex);
+    __builtin_nontemporal_store(wy, Ey);
+    __builtin_nontemporal_store(wz, Ez);
 }
 
 // ---------------------------------------------------------------------------------------------
