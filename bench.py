@@ -175,6 +175,48 @@ def bench_cavities(args):
     }), flush=True)
 
 
+def bench_fp1d(args):
+    """The 1D Fabry-Perot workload (2048 cells, N_b = 16, FP64, 20000 steps): the grid path with graph replay
+    and the on-chip batched path with one cavity."""
+    import torch
+    from fdtdb_inputs import configs
+    from paper_2505_23963_amd import Batch, Grid
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    s = stream.cuda_stream
+    p = configs.config1_1d()
+    steps = args.steps if args.steps != 64 else p.steps
+    out = {}
+    g = Grid(p, stream=s, graph_chunk=128)
+    g.step(args.warmup)
+    g.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    g.synchronize()
+    out["grid_graph"] = p.cells * steps / (time.perf_counter() - t0) / 1e9
+    import copy
+    pb = copy.deepcopy(p)
+    pb.dfts = pb.dfts[:1]          # the batched path keeps one DFT point per cavity (the inside monitor)
+    b = Batch([pb], stream=s)
+    b.step(args.warmup)
+    b.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    dt = time.perf_counter() - t0
+    out["batched_on_chip"] = p.cells * steps / dt / 1e9
+    best = max(out.values())
+    print(json.dumps({
+        "metric": METRIC, "value": round(best, 4), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(p.cells / best / 1e9 * 1e3, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1D Fabry-Perot 2048 cells (PML 64, Drude mirrors, 1800-cell Lorentz-Bath, N_b=16), "
+                               "FP64 state, 512-frequency DFT, energy every 10 steps", "cells": p.cells,
+                   "tiling": list(b.tiling)},
+        "paths": {k: round(v, 4) for k, v in out.items()},
+    }), flush=True)
+
+
 def bench_closure2d(args):
     """Learned closure vs explicit N_b = 64 bath on the 2D 2048^2 TM grid with a 1024^2 Lorentzian-bath
     patch: cell-updates/s of both, and the errors against the explicit run."""
@@ -352,7 +394,7 @@ def main():
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d", "large3d"], default="planar3d",
+    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d", "large3d", "fp1d"], default="planar3d",
                     help="planar3d: the default 256x256x512 line; cavities: the 64-cavity batched 1D workload; "
                          "closure2d: learned closure vs explicit bath on the 2D 2048^2 grid")
     args = ap.parse_args()
@@ -375,6 +417,9 @@ def main():
         return
     if args.workload == "large3d":
         bench_large3d(args)
+        return
+    if args.workload == "fp1d":
+        bench_fp1d(args)
         return
 
     import torch
