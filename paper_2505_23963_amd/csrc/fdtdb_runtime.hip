@@ -274,14 +274,29 @@ double pml_sigma(const fdtdb_grid_s *g, int a, double pos) {
 // Split the grid into boxes of uniform update: cut at every material and CPML edge, then grow
 // boxes greedily (z, then y, then x) over cuts of equal attributes.  E regions carry
 // (material, CPML mask); H regions only the CPML mask (the H update is material-free).
+//
+// The absorbing layer of an axis starts where the grading is nonzero: E-type nodes at p < L and
+// p > n-1-L, H-type nodes (half a cell further along) at p < L and p >= n-1-L.  On the axis the
+// vector kernels run along (z in 3D, y in 2D) the upper H cut is rounded down to a multiple of
+// 4; psi stays exactly zero on the extra nodes, where b = 1 and c = 0.
+int upper_pml_cut(const fdtdb_grid_s *g, int a, bool h) {
+    const int cut = (int)g->n[a] - g->pml[a];
+    if (!h) return cut;
+    const bool vec_axis = (g->ndim == 3 && a == 2) || (g->ndim == 2 && a == 1);
+    return std::max(g->pml[a], vec_axis ? (cut - 1) & ~3 : cut - 1);
+}
+
 void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) {
+    const bool h = !with_mats;
     std::vector<int> br[3];
+    int up[3] = {};
     for (int a = 0; a < 3; a++) {
         br[a].push_back(0);
         br[a].push_back(g->n[a]);
         if (g->bc[a] == FDTDB_BC_PML && a < g->ndim) {
+            up[a] = upper_pml_cut(g, a, h);
             br[a].push_back(g->pml[a]);
-            br[a].push_back(g->n[a] - g->pml[a]);
+            br[a].push_back(up[a]);
         }
         if (with_mats)
             for (auto &m : g->mats) {
@@ -309,7 +324,7 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 }
                 int mask = 0;
                 for (int a = 0; a < g->ndim; a++)
-                    if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= g->n[a] - g->pml[a])) mask |= 1 << a;
+                    if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= up[a])) mask |= 1 << a;
                 auto k = std::make_pair(mat, mask);
                 if (!ids.count(k)) {
                     int id = (int)ids.size();

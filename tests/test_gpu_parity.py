@@ -269,3 +269,34 @@ def test_config2_full_size_sampled(oracle_lib):
         po = o.polarization(1, 0).reshape(2 * h, 2 * h, 400)[h - c:h + c, h - c:h + c]
         pgg = pg.reshape(256, 256, 400)[xs][:, ys]
         assert np.max(np.abs(pgg - po)) <= 1e-5 * np.max(np.abs(po)) + 1e-30
+
+
+# ------------------------------------------------------------------------------------------ CPML
+def _cpml_cases():
+    """A pulse launched next to the upper absorbing layer, run until it has crossed both layers:
+    every E-type and H-type node with nonzero grading carries psi.  Layer thicknesses both
+    divisible and not divisible by 4 (the vector kernels run along z in 3D and y in 2D)."""
+    out = []
+    for L in (8, 10):
+        p = Problem(name=f"cpml1d-L{L}", ndim=1, n=(160, 1, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(L, 0, 0),
+                    dtype="f64", steps=400)
+        p.materials.append(Drude(box((60, 70)), omega_p=0.0, gamma=0.0, eps_inf=4.0))
+        p.sources.append(Source(comp=2, box=box((140, 141)), omega_c=1.0, width=0.6))
+        out.append(p)
+        p = Problem(name=f"cpml2d-L{L}", ndim=2, n=(40, 64, 1), bc=(PML, PML, PERIODIC), pml_cells=(L, L, 0),
+                    dtype="f64", steps=160)
+        p.sources.append(Source(comp=2, box=box((28, 29), (48, 49)), omega_c=1.0, width=0.6))
+        out.append(p)
+        p = Problem(name=f"cpml3d-L{L}", ndim=3, n=(6, 8, 64), bc=(PERIODIC, PERIODIC, PML), pml_cells=(0, 0, L),
+                    dtype="f64", steps=200)
+        p.sources.append(Source(comp=0, box=box((0, 6), (0, 8), (50, 51)), omega_c=1.0, width=0.6))
+        out.append(p)
+    return out
+
+
+@pytest.mark.parametrize("p", _cpml_cases(), ids=lambda p: p.name)
+def test_cpml_layers_fp64(oracle_lib, p):
+    g, o = run_pair(oracle_lib, p)
+    errs = rel_fields(g, o, fields_of(p))
+    print("rel-L2 per component:", errs, flush=True)
+    assert max(errs.values()) < 1e-12, errs
