@@ -115,6 +115,9 @@ struct RegionDesc {
     int block0;
     double inv_eps;
     void *psi[3][2];
+    // 3D H regions: psi of the z terms only for z < zlo and z >= zhi, stored per row in
+    // zw = (zlo - lo[2]) + (lo[2] + ext[2] - zhi) slots; zw = 0: psi per cell of the region
+    int zlo, zhi, zw;
 };
 constexpr int kMaxGroup = 32;
 // region table of a grouped launch: first blocks (unused entries hold INT_MAX, so every entry can

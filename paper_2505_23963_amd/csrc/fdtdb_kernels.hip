@@ -664,6 +664,7 @@ __device__ __forceinline__ double lane4(const vec4_t<T> &v, int e) {
 // region of a v4 launch (always from the table) and the first of the thread's 4 z-cells
 struct Cell4 {
     int i, j, k, tc;       // cell of the first z value, region-local index of that cell
+    int row;               // region-local row (x, y) of a 3D cell
     bool live;
 };
 template <class A>
@@ -683,21 +684,56 @@ __device__ __forceinline__ const RegionDesc &v4_region(const A &a, Cell4 &c) {
     c.i = D.lo[0] + r2;
     c.j = D.lo[1] + (rr - r2 * D.ext[1]);
     c.tc = 4 * t;
+    c.row = rr;
     return D;
 }
 
 // CPML convolution of one curl term for 4 z-consecutive cells: psi <- b psi + c dF, dF += psi
+// Coefficients of the 4 cells: along the vector axis they differ per cell and are read as two
+// 16-byte pairs (the first cell is 4-aligned, the tables 256-byte aligned); across it they are
+// one value.
+__device__ __forceinline__ void coef4(const double *t, bool along, int x, double *out) {
+    if (along) {
+        const double2 lo = *reinterpret_cast<const double2 *>(t + x);
+        const double2 hi = *reinterpret_cast<const double2 *>(t + x + 2);
+        out[0] = lo.x; out[1] = lo.y; out[2] = hi.x; out[3] = hi.y;
+    } else {
+        const double v = t[x];
+        out[0] = v; out[1] = v; out[2] = v; out[3] = v;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void cpml4(void *psi, int tc, int ax, int i, int j, int k, const double *pb,
                                       const double *pc, double *term) {
     using V = vec4_t<T>;
     V *pp = reinterpret_cast<V *>(static_cast<T *>(psi) + tc);
     const V p = *pp;
-    double o[4];
+    const int x = ax == 0 ? i : ax == 1 ? j : k;
+    double b[4], c[4], o[4];
+    coef4(pb, ax == 2, x, b);
+    coef4(pc, ax == 2, x, c);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int x = ax == 0 ? i : ax == 1 ? j : k + e;
-        o[e] = pb[x] * lane4<T>(p, e) + pc[x] * term[e];
+        o[e] = b[e] * lane4<T>(p, e) + c[e] * term[e];
+        term[e] += o[e];
+    }
+    V w;
+    w.x = (T)o[0]; w.y = (T)o[1]; w.z = (T)o[2]; w.w = (T)o[3];
+    *pp = w;
+}
+
+// The same convolution with psi already loaded (prefetched with the field rows)
+template <typename T>
+__device__ __forceinline__ void cpml4_apply(const vec4_t<T> &p, vec4_t<T> *pp, int k, const double *pb,
+                                            const double *pc, double *term) {
+    using V = vec4_t<T>;
+    double b[4], c[4], o[4];
+    coef4(pb, true, k, b);
+    coef4(pc, true, k, c);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        o[e] = b[e] * lane4<T>(p, e) + c[e] * term[e];
         term[e] += o[e];
     }
     V w;
@@ -738,6 +774,23 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     NV *Hy = reinterpret_cast<NV *>(static_cast<T *>(a.H[1]) + q);
     NV *Hz = reinterpret_cast<NV *>(static_cast<T *>(a.H[2]) + q);
     const NV hxn = __builtin_nontemporal_load(Hx), hyn = __builtin_nontemporal_load(Hy), hzn = __builtin_nontemporal_load(Hz);
+    // z-term psi (Hx's and Hy's): per cell of the region, or (zw > 0) only for z < zlo and
+    // z >= zhi, in zw slots per row (the 4-cell groups never straddle zlo or zhi); loaded here so
+    // that its latency overlaps that of the field rows
+    V *pz0 = nullptr, *pz1 = nullptr;
+    {
+        int tz = C.tc;
+        bool zon = true;
+        if (D.zw) {
+            zon = k < D.zlo || k >= D.zhi;
+            tz = C.row * D.zw + (k < D.zlo ? k - D.lo[2] : k - D.zhi + (D.zlo - D.lo[2]));
+        }
+        if (zon && D.psi[0][1]) pz0 = reinterpret_cast<V *>(static_cast<T *>(D.psi[0][1]) + tz);
+        if (zon && D.psi[1][0]) pz1 = reinterpret_cast<V *>(static_cast<T *>(D.psi[1][0]) + tz);
+    }
+    V psz0{}, psz1{};
+    if (pz0) psz0 = *pz0;
+    if (pz1) psz1 = *pz1;
     V hx, hy, hz;
     hx.x = hxn[0]; hx.y = hxn[1]; hx.z = hxn[2]; hx.w = hxn[3];
     hy.x = hyn[0]; hy.y = hyn[1]; hy.z = hyn[2]; hy.w = hyn[3];
@@ -757,8 +810,8 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
         tz1[e] = eyx - eye; tz2[e] = exy - exe;
     }
     if (D.psi[0][0]) cpml4<T>(D.psi[0][0], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tx1);
-    if (D.psi[0][1]) cpml4<T>(D.psi[0][1], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], tx2);
-    if (D.psi[1][0]) cpml4<T>(D.psi[1][0], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], ty1);
+    if (pz0) cpml4_apply<T>(psz0, pz0, k, a.pml_b[2], a.pml_c[2], tx2);
+    if (pz1) cpml4_apply<T>(psz1, pz1, k, a.pml_b[2], a.pml_c[2], ty1);
     if (D.psi[1][1]) cpml4<T>(D.psi[1][1], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], ty2);
     if (D.psi[2][0]) cpml4<T>(D.psi[2][0], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], tz1);
     if (D.psi[2][1]) cpml4<T>(D.psi[2][1], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tz2);
@@ -807,11 +860,13 @@ __device__ __forceinline__ void cpml4y(void *psi, int tc, int ax, int i, int j, 
     using V = vec4_t<T>;
     V *pp = reinterpret_cast<V *>(static_cast<T *>(psi) + tc);
     const V p = *pp;
-    double o[4];
+    const int x = ax == 0 ? i : j;
+    double b[4], c[4], o[4];
+    coef4(pb, ax == 1, x, b);
+    coef4(pc, ax == 1, x, c);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int x = ax == 0 ? i : j + e;
-        o[e] = pb[x] * lane4<T>(p, e) + pc[x] * term[e];
+        o[e] = b[e] * lane4<T>(p, e) + c[e] * term[e];
         term[e] += o[e];
     }
     V w;
@@ -937,6 +992,19 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     NV *Ey = reinterpret_cast<NV *>(static_cast<T *>(a.E[1]) + q);
     NV *Ez = reinterpret_cast<NV *>(static_cast<T *>(a.E[2]) + q);
     const NV exn = __builtin_nontemporal_load(Ex), eyn = __builtin_nontemporal_load(Ey), ezn = __builtin_nontemporal_load(Ez);
+    // the Drude increments and the z-term psi (Ex's, Ey's) are loaded with the field rows, so that
+    // their latency overlaps
+    NV vv[3];
+    const int m = DRUDE ? ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]) : 0;
+    if (DRUDE) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vv[c] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(static_cast<const T *>(a.Pcur[c]) + m));
+    }
+    V *pz0 = D.psi[0][1] ? reinterpret_cast<V *>(static_cast<T *>(D.psi[0][1]) + C.tc) : nullptr;
+    V *pz1 = D.psi[1][0] ? reinterpret_cast<V *>(static_cast<T *>(D.psi[1][0]) + C.tc) : nullptr;
+    V psz0{}, psz1{};
+    if (pz0) psz0 = *pz0;
+    if (pz1) psz1 = *pz1;
     V ex, ey, ez;
     ex.x = exn[0]; ex.y = exn[1]; ex.z = exn[2]; ex.w = exn[3];
     ey.x = eyn[0]; ey.y = eyn[1]; ey.z = eyn[2]; ey.w = eyn[3];
@@ -955,8 +1023,8 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
         tz1[e] = hye - hyx; tz2[e] = hxe - hxy;
     }
     if (D.psi[0][0]) cpml4<T>(D.psi[0][0], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tx1);
-    if (D.psi[0][1]) cpml4<T>(D.psi[0][1], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], tx2);
-    if (D.psi[1][0]) cpml4<T>(D.psi[1][0], C.tc, 2, i, j, k, a.pml_b[2], a.pml_c[2], ty1);
+    if (pz0) cpml4_apply<T>(psz0, pz0, k, a.pml_b[2], a.pml_c[2], tx2);
+    if (pz1) cpml4_apply<T>(psz1, pz1, k, a.pml_b[2], a.pml_c[2], ty1);
     if (D.psi[1][1]) cpml4<T>(D.psi[1][1], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], ty2);
     if (D.psi[2][0]) cpml4<T>(D.psi[2][0], C.tc, 0, i, j, k, a.pml_b[0], a.pml_c[0], tz1);
     if (D.psi[2][1]) cpml4<T>(D.psi[2][1], C.tc, 1, i, j, k, a.pml_b[1], a.pml_c[1], tz2);
@@ -966,7 +1034,6 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     double ox[4], oy[4], oz[4];
     if (DRUDE) {
         // Drude: E^{n+1/2} = E^{n-1/2} + (dt curl H - V) / eps - dt J / eps;  V' = dE E^{n+1/2} + dV V
-        const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
         const double dE = a.coef[0], dV = a.coef[1];
         double *o3[3] = {ox, oy, oz};
         const V *ev[3] = {&ex, &ey, &ez};
@@ -974,12 +1041,11 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             nvec4_t<T> *Vp = reinterpret_cast<nvec4_t<T> *>(static_cast<T *>(a.Pcur[c]) + m);
-            const nvec4_t<T> vv = __builtin_nontemporal_load(Vp);
             nvec4_t<T> vn;
             double vo[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const double v = (double)vv[e];
+                const double v = (double)vv[c][e];
                 o3[c][e] = lane4<T>(*ev[c], e) + D.inv_eps * (a.dt * (t1s[c][e] - t2s[c][e]) - v) -
                            source_term(a, amp, c, i, j, k + e);
                 vo[e] = dE * o3[c][e] + dV * v;

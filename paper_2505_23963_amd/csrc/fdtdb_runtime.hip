@@ -88,7 +88,11 @@ struct Region {
     void *psiH[3][2] = {};
     bool energy = false;
     long long block_base = 0;
+    // H only: z-term psi for z < zlo and z >= zhi alone, in zw = (zlo - lo) + (hi - zhi) slots per
+    // row; zw = 0: per cell of the region
+    int zlo = 0, zhi = 0, zw = 0;
     long long cells() const { return (long long)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+    long long psi_words(int axis) const { return zw && axis == 2 ? cells() / (hi[2] - lo[2]) * zw : cells(); }
 };
 
 // one kernel launch of a step: a single region, or a group of background regions (grouped
@@ -276,14 +280,23 @@ double pml_sigma(const fdtdb_grid_s *g, int a, double pos) {
 // (material, CPML mask); H regions only the CPML mask (the H update is material-free).
 //
 // The absorbing layer of an axis starts where the grading is nonzero: E-type nodes at p < L and
-// p > n-1-L, H-type nodes (half a cell further along) at p < L and p >= n-1-L.  On the axis the
-// vector kernels run along (z in 3D, y in 2D) the upper H cut is rounded down to a multiple of
-// 4; psi stays exactly zero on the extra nodes, where b = 1 and c = 0.
+// p > n-1-L, H-type nodes (half a cell further along) at p < L and p >= n-1-L.  In 3D with
+// 4-aligned z layers the H regions are cut along z where the E regions are, and the region
+// below the upper layer carries psi for its last 4-cell z group only (the node at n-1-L and
+// three nodes where b = 1, c = 0 and psi stays exactly zero), in 4 slots per row: row splits
+// then stay on 128-byte lines.  Otherwise, on the axis the vector kernels run along (z in 3D,
+// y in 2D) the upper H cut is rounded down to a multiple of 32 cells for the same reason (a line
+// shared by two regions is fetched and partially written by both); psi is again zero on the
+// extra nodes.
+bool z_tail_h(const fdtdb_grid_s *g) {
+    return g->ndim == 3 && g->bc[2] == FDTDB_BC_PML && g->n[2] % 4 == 0 && g->pml[2] % 4 == 0;
+}
+
 int upper_pml_cut(const fdtdb_grid_s *g, int a, bool h) {
     const int cut = (int)g->n[a] - g->pml[a];
-    if (!h) return cut;
+    if (!h || (a == 2 && z_tail_h(g))) return cut;
     const bool vec_axis = (g->ndim == 3 && a == 2) || (g->ndim == 2 && a == 1);
-    return std::max(g->pml[a], vec_axis ? (cut - 1) & ~3 : cut - 1);
+    return std::max(g->pml[a], vec_axis ? (cut - 1) & ~31 : cut - 1);
 }
 
 void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) {
@@ -375,15 +388,23 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
 fdtdb_status build_regions(fdtdb_grid_s *g) {
     partition(g, true, g->regions);
     partition(g, false, g->hregions);
+    if (z_tail_h(g) && g->pml[2] > 0)
+        for (auto &r : g->hregions)
+            if (r.hi[2] == (int)g->n[2] - g->pml[2] && !(r.pml_mask & (1 << 2))) {
+                r.pml_mask |= 1 << 2;
+                r.zlo = r.lo[2];
+                r.zhi = std::max(r.lo[2], r.hi[2] - 4);
+                r.zw = r.hi[2] - r.zhi;
+            }
     // CPML psi storage per region, per component and curl term whose axis is absorbing
     for (int h = 0; h < 2; h++)
         for (auto &r : h ? g->hregions : g->regions) {
             if (!r.pml_mask) continue;
-            const long long nc_ = r.cells();
             for (int c = 0; c < 3; c++) {
                 const int ax[2] = {curl_a1(c), curl_a2(c)};
                 for (int t = 0; t < 2; t++) {
                     if (!(r.pml_mask & (1 << ax[t]))) continue;
+                    const long long nc_ = r.psi_words(ax[t]);
                     if (!h && e_active(g->ndim, c)) TRY(g->alloc(&r.psiE[c][t], words(nc_, g->f64)));
                     if (h && h_active(g->ndim, c)) TRY(g->alloc(&r.psiH[c][t], words(nc_, g->f64)));
                 }
@@ -406,9 +427,13 @@ void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh
     for (int c = 0; c < 3; c++) { ne += e_active(g->ndim, c); nh += h_active(g->ndim, c); }
     double e = (2.0 * ne + nh) * w, h = (ne + 2.0 * nh) * w;
     if (r.pml_mask) {
-        int te = 0, th = 0;
+        int te = 0;
+        double th = 0.0;
         for (int c = 0; c < 3; c++)
-            for (int t = 0; t < 2; t++) { te += r.psiE[c][t] != nullptr; th += r.psiH[c][t] != nullptr; }
+            for (int t = 0; t < 2; t++) {
+                te += r.psiE[c][t] != nullptr;
+                if (r.psiH[c][t]) th += (double)r.psi_words(t ? curl_a2(c) : curl_a1(c)) / (double)r.cells();
+            }
         e += 2.0 * te * w;
         h += 2.0 * th * w;
     }
@@ -513,7 +538,11 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         make(g->elaunch, g->regions, drude4, false, true);
         make(g->elaunch, g->regions, solo, false, false);
         std::vector<int> h4, hg;
-        for (int i = 0; i < (int)g->hregions.size(); i++) (z4(g->hregions[i]) ? h4 : hg).push_back(i);
+        for (int i = 0; i < (int)g->hregions.size(); i++) {
+            if (g->hregions[i].zw && !z4(g->hregions[i]))   // per-row psi slots: vector kernel only
+                return fail(FDTDB_E_STATE, "H region with per-row psi slots but no 4-aligned z range");
+            (z4(g->hregions[i]) ? h4 : hg).push_back(i);
+        }
         make(g->hlaunch, g->hregions, h4, true, true);
         make(g->hlaunch, g->hregions, hg, hg.size() > 1, false);
     }
@@ -541,6 +570,9 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
                 x.inv_eps = 1.0 / rg.eps;
                 for (int c = 0; c < 3; c++)
                     for (int t = 0; t < 2; t++) x.psi[c][t] = ph ? rg.psiH[c][t] : rg.psiE[c][t];
+                x.zlo = rg.zlo;
+                x.zhi = rg.zhi;
+                x.zw = rg.zw;
             }
             TRY(g->alloc((void **)&L.rd, sizeof(RegionTable)));
             HIP_TRY(hipMemcpy(L.rd, &tab, sizeof(RegionTable), hipMemcpyHostToDevice));
