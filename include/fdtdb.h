@@ -192,6 +192,21 @@ fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps);
  * (rounded up to an even count) and replay them. Requires a non-NULL stream. */
 fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps);
 
+/* Checkpoint and resume of the leapfrog state (Sec. II: H^n, E^{n+1/2}; eq:Pz_update-LB and
+ * eq:Yzj_finite_difference: both time levels of P and of every bath coordinate Y_j; the CPML psi
+ * of every absorbing cell; the learned closure's hidden state; the FP64 DFT accumulators and
+ * their unflushed staging slots; the energy samples so far; probe records; the step counter and
+ * source clock).  save_state synchronizes the stream and writes one binary file (host path,
+ * overwritten; nothing of the caller's is retained).  load_state reads such a file into a grid
+ * built with the same set-up (geometry, dtype, materials and their parameters, sources,
+ * monitors, probes; the closure weights themselves are not compared), after which stepping
+ * continues exactly as the saved grid would have: a resumed run equals an uninterrupted one
+ * bitwise.  Errors: E_INVALID for null arguments or a file that cannot be opened or written;
+ * E_STATE for a file that is not a state file, is truncated, or was written by a grid with
+ * another set-up (the grid is then left unchanged); E_DEVICE on a device copy failure. */
+fdtdb_status fdtdb_save_state(fdtdb_grid g, const char *path);
+fdtdb_status fdtdb_load_state(fdtdb_grid g, const char *path);
+
 /* ------------------------------------------------------------------------------------- read-out */
 /* All read-outs synchronize the grid's stream first. */
 

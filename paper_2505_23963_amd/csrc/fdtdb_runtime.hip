@@ -181,6 +181,7 @@ struct fdtdb_grid_s {
     int graph_parity = 0;
     int launches_per_step = 0;
     std::vector<void *> allocs;
+    std::map<void *, size_t> sizes;   // bytes of every live allocation (checkpoint layout)
     // profiling
     int profiling = 0;             // 0 off, 1 every E/H launch, 2 dispersive-material E launches only
     std::vector<fdtdb_kernel_record> records;
@@ -194,10 +195,12 @@ struct fdtdb_grid_s {
         e = hipMemset(*p, 0, bytes);
         if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(*p);
+        sizes[*p] = bytes;
         return FDTDB_OK;
     }
     void release(void *&p) {
         if (!p) return;
+        sizes.erase(p);
         for (auto &q : allocs)
             if (q == p) {
                 (void)hipFree(q);
@@ -847,6 +850,85 @@ fdtdb_status write_state(fdtdb_grid_s *g, void *dst, long long n, const double *
 }  // namespace
 
 // ============================================================================ C ABI
+// ---------------------------------------------------------------------------- checkpoint
+namespace {
+
+constexpr char kStateMagic[8] = {'F', 'D', 'T', 'D', 'B', 'S', 'T', '1'};
+
+// FNV-1a over the set-up of the grid: two grids with the same fingerprint have the same state
+// buffers with the same meaning
+struct Fnv {
+    uint64_t h = 1469598103934665603ULL;
+    void bytes(const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; i++) { h ^= c[i]; h *= 1099511628211ULL; }
+    }
+    template <class T> void v(const T &x) { bytes(&x, sizeof x); }
+    void vec(const std::vector<double> &x) { v(x.size()); if (!x.empty()) bytes(x.data(), 8 * x.size()); }
+};
+
+uint64_t fingerprint(const fdtdb_grid_s *g) {
+    Fnv f;
+    f.v(g->ndim); f.bytes(g->n, sizeof g->n); f.v(g->dt); f.v(g->R0); f.v(g->f64);
+    f.bytes(g->bc, sizeof g->bc); f.bytes(g->pml, sizeof g->pml);
+    f.v(g->mats.size());
+    for (auto &m : g->mats) {
+        f.v(m.kind); f.bytes(m.lo, sizeof m.lo); f.bytes(m.hi, sizeof m.hi); f.v(m.eps); f.v(m.omega0);
+        f.v(m.gamma0); f.v(m.sigma0); f.v(m.sigma_per_cell); f.v(m.nb); f.vec(m.wj); f.vec(m.gj); f.vec(m.kj);
+        f.vec(m.coef); f.v(m.cw_dev != nullptr); f.bytes(m.cscale, sizeof m.cscale);
+    }
+    f.v(g->srcs.size());
+    for (auto &x : g->srcs) {
+        f.v(x.comp); f.bytes(x.lo, sizeof x.lo); f.bytes(x.hi, sizeof x.hi); f.v(x.omega_c); f.v(x.width);
+        f.v(x.amplitude); f.vec(x.profile);
+    }
+    f.v(g->dfts.size());
+    for (auto &d : g->dfts) { f.v(d.axis); f.bytes(d.lo, sizeof d.lo); f.bytes(d.hi, sizeof d.hi); f.vec(d.omega); }
+    f.v(g->ens.size());
+    for (auto &e : g->ens) { f.bytes(e.lo, sizeof e.lo); f.bytes(e.hi, sizeof e.hi); f.v(e.every); }
+    f.v(g->probes.size());
+    for (auto &p : g->probes) { f.v(p.mat); f.v(p.comp); f.v(p.n); f.v(p.capacity); }
+    return f.h;
+}
+
+// every device buffer whose contents evolve with the steps, in a fixed order; energy sample
+// buffers only up to the samples taken in the first `steps` steps
+fdtdb_status state_buffers(const fdtdb_grid_s *g, long long steps, std::vector<std::pair<void *, size_t>> &out) {
+    auto add = [&](void *p) -> fdtdb_status {
+        if (!p) return FDTDB_OK;
+        auto it = g->sizes.find(p);
+        if (it == g->sizes.end()) return fail(FDTDB_E_STATE, "state buffer without a recorded size");
+        out.emplace_back(p, it->second);
+        return FDTDB_OK;
+    };
+    out.emplace_back(g->clock, sizeof(Clock));
+    for (int c = 0; c < 3; c++) { TRY(add(g->E[c])); TRY(add(g->H[c])); }
+    for (auto &m : g->mats) {
+        for (int l = 0; l < 2; l++)
+            for (int c = 0; c < 3; c++) { TRY(add(m.P[l][c])); TRY(add(m.Y[l][c])); }
+        for (int c = 0; c < 3; c++) TRY(add(m.hid[c]));
+    }
+    for (int h = 0; h < 2; h++)
+        for (auto &r : h ? g->hregions : g->regions)
+            for (int c = 0; c < 3; c++)
+                for (int t = 0; t < 2; t++) TRY(add(h ? r.psiH[c][t] : r.psiE[c][t]));
+    for (auto &d : g->dfts) { TRY(add(d.stage)); TRY(add(d.acc)); }
+    for (auto &e : g->ens) {
+        const long long n = steps == 0 ? 0 : (steps - 1) / e.every + 1;
+        if (n > e.capacity) return fail(FDTDB_E_STATE, "energy buffer smaller than its samples");
+        if (n > 0) out.emplace_back(e.out, 24 * (size_t)n);
+    }
+    for (auto &p : g->probes) { TRY(add(p.E)); TRY(add(p.P)); }
+    return FDTDB_OK;
+}
+
+struct File {
+    FILE *f = nullptr;
+    ~File() { if (f) fclose(f); }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char *fdtdb_last_error(void) { return g_err.c_str(); }
@@ -1387,6 +1469,80 @@ fdtdb_status fdtdb_get_bath(fdtdb_grid g, int mid, int c, int level, double *out
     // device layout [group][cell][4] -> [mode][cell]
     for (int jb = 0; jb < m.nb; jb++)
         for (long long q = 0; q < m.mcells; q++) out[(size_t)jb * m.mcells + q] = tmp[((size_t)(jb / 4) * m.mcells + q) * 4 + (jb & 3)];
+    return FDTDB_OK;
+}
+
+
+fdtdb_status fdtdb_save_state(fdtdb_grid g, const char *path) {
+    if (!g || !path) return fail(FDTDB_E_INVALID, "null argument");
+    TRY(finalize(g));
+    std::vector<std::pair<void *, size_t>> bufs;
+    TRY(state_buffers(g, g->steps, bufs));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    File fl;
+    fl.f = fopen(path, "wb");
+    if (!fl.f) return fail(FDTDB_E_INVALID, "cannot open %s for writing", path);
+    const uint64_t fp = fingerprint(g);
+    const int64_t steps = g->steps;
+    const int32_t nbuf = (int32_t)bufs.size(), ndft = (int32_t)g->dfts.size();
+    bool ok = fwrite(kStateMagic, 1, 8, fl.f) == 8 && fwrite(&fp, 8, 1, fl.f) == 1 && fwrite(&steps, 8, 1, fl.f) == 1 &&
+              fwrite(&nbuf, 4, 1, fl.f) == 1 && fwrite(&ndft, 4, 1, fl.f) == 1;
+    for (auto &d : g->dfts) {
+        const int32_t ns = d.nstaged;
+        ok = ok && fwrite(&ns, 4, 1, fl.f) == 1;
+    }
+    std::vector<char> host;
+    for (auto &b : bufs) {
+        if (!ok) break;
+        const uint64_t nb = b.second;
+        host.resize(nb);
+        HIP_TRY(hipMemcpy(host.data(), b.first, nb, hipMemcpyDeviceToHost));
+        ok = fwrite(&nb, 8, 1, fl.f) == 1 && fwrite(host.data(), 1, nb, fl.f) == nb;
+    }
+    if (!ok) return fail(FDTDB_E_INVALID, "write to %s failed", path);
+    if (fclose(fl.f) != 0) { fl.f = nullptr; return fail(FDTDB_E_INVALID, "closing %s failed", path); }
+    fl.f = nullptr;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_load_state(fdtdb_grid g, const char *path) {
+    if (!g || !path) return fail(FDTDB_E_INVALID, "null argument");
+    TRY(finalize(g));
+    File fl;
+    fl.f = fopen(path, "rb");
+    if (!fl.f) return fail(FDTDB_E_INVALID, "cannot open %s", path);
+    char magic[8];
+    uint64_t fp = 0;
+    int64_t steps = 0;
+    int32_t nbuf = 0, ndft = 0;
+    if (fread(magic, 1, 8, fl.f) != 8 || memcmp(magic, kStateMagic, 8) != 0)
+        return fail(FDTDB_E_STATE, "%s is not a grid state file", path);
+    if (fread(&fp, 8, 1, fl.f) != 1 || fread(&steps, 8, 1, fl.f) != 1 || fread(&nbuf, 4, 1, fl.f) != 1 ||
+        fread(&ndft, 4, 1, fl.f) != 1 || steps < 0)
+        return fail(FDTDB_E_STATE, "truncated header in %s", path);
+    if (fp != fingerprint(g) || ndft != (int32_t)g->dfts.size())
+        return fail(FDTDB_E_STATE, "%s was written by a grid with another set-up", path);
+    std::vector<int32_t> staged(ndft);
+    for (auto &ns : staged)
+        if (fread(&ns, 4, 1, fl.f) != 1 || ns < 0 || ns >= kDftSlots) return fail(FDTDB_E_STATE, "bad header in %s", path);
+    TRY(ensure_energy_capacity(g, steps));
+    std::vector<std::pair<void *, size_t>> bufs;
+    TRY(state_buffers(g, steps, bufs));
+    if ((size_t)nbuf != bufs.size()) return fail(FDTDB_E_STATE, "%s holds %d buffers, the grid %zu", path, nbuf, bufs.size());
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    // read everything before touching the device, so that a short file leaves the grid unchanged
+    std::vector<std::vector<char>> host(bufs.size());
+    for (size_t i = 0; i < bufs.size(); i++) {
+        uint64_t nb = 0;
+        if (fread(&nb, 8, 1, fl.f) != 1 || nb != bufs[i].second)
+            return fail(FDTDB_E_STATE, "buffer %zu of %s has the wrong size", i, path);
+        host[i].resize(nb);
+        if (fread(host[i].data(), 1, nb, fl.f) != nb) return fail(FDTDB_E_STATE, "truncated buffer %zu in %s", i, path);
+    }
+    for (size_t i = 0; i < bufs.size(); i++)
+        HIP_TRY(hipMemcpy(bufs[i].first, host[i].data(), bufs[i].second, hipMemcpyHostToDevice));
+    g->steps = steps;
+    for (size_t i = 0; i < g->dfts.size(); i++) g->dfts[i].nstaged = staged[i];
     return FDTDB_OK;
 }
 

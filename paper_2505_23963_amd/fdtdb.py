@@ -71,6 +71,8 @@ SIGNATURES = [
     ("fdtdb_synchronize", C.c_int, [C.c_void_p]),
     ("fdtdb_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("fdtdb_set_graph", C.c_int, [C.c_void_p, C.c_int]),
+    ("fdtdb_save_state", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("fdtdb_load_state", C.c_int, [C.c_void_p, C.c_char_p]),
     ("fdtdb_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp, _dp]),
     ("fdtdb_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
     ("fdtdb_get_field", C.c_int, [C.c_void_p, C.c_int, _dp]),
@@ -324,6 +326,14 @@ class Grid:
         out = np.zeros(3 * max(n.value, 1), np.float64)
         _check(lib().fdtdb_energy(self.h, mid, _ptr(out), n.value, C.byref(n)))
         return out[:3 * n.value].reshape(-1, 3)
+
+    def save_state(self, path: str):
+        """Write the whole time-stepping state to a file (fdtdb_save_state)."""
+        _check(lib().fdtdb_save_state(self.h, os.fsencode(path)))
+
+    def load_state(self, path: str):
+        """Resume from a file written by save_state on a grid of the same set-up."""
+        _check(lib().fdtdb_load_state(self.h, os.fsencode(path)))
 
     def set_profiling(self, on, dispersive_only: bool = False):
         """Events around every E/H launch (on), or only around dispersive-material E launches."""

@@ -131,3 +131,12 @@ def test_trainer_and_batch_reject_bad_descriptors(libfdtdb):
     lens = (ctypes.c_int64 * 2)(100, 0)
     assert L.fdtdb_batch_create(2, lens, 0, 0.5, 8, 1e-8, None, ctypes.byref(h)) == -1     # empty cavity
     assert L.fdtdb_batch_create(0, lens, 0, 0.5, 8, 1e-8, None, ctypes.byref(h)) == -1     # no cavities
+
+
+def test_checkpoint_entry_points_reject_null_arguments(libfdtdb):
+    """save_state / load_state check their arguments on the host before any device work."""
+    from paper_2505_23963_amd import lib
+    L = lib()
+    for fn in (L.fdtdb_save_state, L.fdtdb_load_state):
+        assert fn(None, b"/tmp/x.state") == -1
+        assert b"null" in L.fdtdb_last_error()
