@@ -383,6 +383,20 @@ const char *fdtdb_last_error(void);
 /* Library version string. */
 const char *fdtdb_version(void);
 
+/* ------------------------------------------------------------------------------------- memory */
+/* Device memory source (not from the paper: an ownership hook for callers with their own device
+ * allocator, such as a framework's caching allocator).  Grids, batches and trainers created after
+ * the call take every device buffer from alloc(bytes, ctx), which must return memory of the
+ * current device, aligned to 256 bytes, or NULL (the creating call then fails with E_NOMEM; a
+ * misaligned block is handed back to free and also gives E_NOMEM); they release it through
+ * free(ptr, ctx) when destroyed.  Each object keeps the allocator it was created with, so the
+ * callbacks and ctx must stay valid until the last such object is destroyed.  Both NULL restores
+ * hipMalloc / hipFree (the default).  E_INVALID if exactly one of them is NULL.  Host-only; the
+ * setting is process-wide and guarded by a lock. */
+typedef void *(*fdtdb_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fdtdb_free_fn)(void *ptr, void *ctx);
+fdtdb_status fdtdb_set_allocator(fdtdb_alloc_fn alloc, fdtdb_free_fn free_fn, void *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -471,10 +471,11 @@ struct fdtdb_batch_s {
     int graph_steps = 0;
     std::vector<std::pair<void **, size_t>> state;   // device state arrays and their sizes (autotune scratch)
 
+    DevAllocator mem = current_allocator();
     fdtdb_status alloc(void **p, size_t bytes) {
         if (bytes == 0) bytes = 8;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) return bfail(FDTDB_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        hipError_t e = dev_alloc(mem, p, bytes);
+        if (e != hipSuccess) return bfail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
         e = hipMemset(*p, 0, bytes);
         if (e != hipSuccess) return bfail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(*p);
@@ -687,7 +688,7 @@ fdtdb_status autotune(fdtdb_batch_s *b) {
     for (size_t i = 0; i < b->state.size(); i++) {
         real[i] = *b->state[i].first;
         void *p = nullptr;
-        BHIP(hipMalloc(&p, b->state[i].second));
+        BHIP(dev_alloc(b->mem, &p, b->state[i].second));
         BHIP(hipMemcpyAsync(p, real[i], b->state[i].second, hipMemcpyDeviceToDevice, b->stream));
         scratch[i] = p;
         *b->state[i].first = p;
@@ -728,7 +729,7 @@ fdtdb_status autotune(fdtdb_batch_s *b) {
     (void)hipStreamSynchronize(b->stream);
     for (size_t i = 0; i < b->state.size(); i++) {
         *b->state[i].first = real[i];
-        (void)hipFree(scratch[i]);
+        dev_free(b->mem, scratch[i]);
     }
     b->args.en_part = en_saved;
     b->args.en_cap = cap_saved;
@@ -784,7 +785,7 @@ fdtdb_status fdtdb_batch_destroy(fdtdb_batch b) {
     if (!b) return FDTDB_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    for (void *p : b->allocs) (void)hipFree(p);
+    for (void *p : b->allocs) dev_free(b->mem, p);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return FDTDB_OK;
@@ -999,11 +1000,11 @@ fdtdb_status fdtdb_batch_dft_flux(fdtdb_batch b, int cav, double *flux) {
     BTRY(finalize(b));
     double *d;
     const int nf = (int)b->omega.size();
-    BHIP(hipMalloc(&d, 8 * (size_t)nf));
+    BHIP(dev_alloc(b->mem, (void **)&d, 8 * (size_t)nf));
     hipLaunchKernelGGL(k_batch_flux, dim3((nf + 255) / 256), dim3(256), 0, b->stream, b->args.dft_acc, nf, cav, d);
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipMemcpy(flux, d, 8 * (size_t)nf, hipMemcpyDeviceToHost);
-    (void)hipFree(d);
+    dev_free(b->mem, d);
     if (e != hipSuccess) return bfail(FDTDB_E_DEVICE, "flux read-out: %s", hipGetErrorString(e));
     return FDTDB_OK;
 }
@@ -1016,12 +1017,12 @@ fdtdb_status fdtdb_batch_energy(fdtdb_batch b, int cav, double *out, int64_t cap
     const long long m = std::min<long long>(n, capacity);
     if (!out || m <= 0) return FDTDB_OK;
     double *d;
-    BHIP(hipMalloc(&d, 24 * (size_t)m));
+    BHIP(dev_alloc(b->mem, (void **)&d, 24 * (size_t)m));
     hipLaunchKernelGGL(k_batch_energy, dim3((m + 255) / 256), dim3(256), 0, b->stream, b->args.en_part, b->seg_slots,
                        b->en_cap, cav, (int)m, d);
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipMemcpy(out, d, 24 * (size_t)m, hipMemcpyDeviceToHost);
-    (void)hipFree(d);
+    dev_free(b->mem, d);
     if (e != hipSuccess) return bfail(FDTDB_E_DEVICE, "energy read-out: %s", hipGetErrorString(e));
     return FDTDB_OK;
 }

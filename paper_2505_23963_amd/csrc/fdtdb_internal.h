@@ -202,4 +202,15 @@ struct BathCoef {
 constexpr int kCoefHead = 8;
 constexpr int kCoefMode = 8;
 
+// Device memory source of a grid, batch or trainer: the process-wide allocator at the object's
+// creation (null callbacks: hipMalloc / hipFree).  Blocks are required to be 256-byte aligned.
+struct DevAllocator {
+    void *(*alloc)(size_t, void *);
+    void (*free)(void *, void *);
+    void *ctx;
+};
+DevAllocator current_allocator();
+hipError_t dev_alloc(const DevAllocator &a, void **p, size_t bytes);
+void dev_free(const DevAllocator &a, void *p);
+
 }  // namespace fdtdb

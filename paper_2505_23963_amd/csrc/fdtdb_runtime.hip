@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -188,10 +189,11 @@ struct fdtdb_grid_s {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
 
+    DevAllocator mem = current_allocator();
     fdtdb_status alloc(void **p, size_t bytes) {
         if (bytes == 0) bytes = 8;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) return fail(FDTDB_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        hipError_t e = dev_alloc(mem, p, bytes);
+        if (e != hipSuccess) return fail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
         e = hipMemset(*p, 0, bytes);
         if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(*p);
@@ -203,7 +205,7 @@ struct fdtdb_grid_s {
         sizes.erase(p);
         for (auto &q : allocs)
             if (q == p) {
-                (void)hipFree(q);
+                dev_free(mem, q);
                 q = allocs.back();
                 allocs.pop_back();
                 break;
@@ -850,6 +852,35 @@ fdtdb_status write_state(fdtdb_grid_s *g, void *dst, long long n, const double *
 }  // namespace
 
 // ============================================================================ C ABI
+// ---------------------------------------------------------------------------- device memory
+namespace {
+std::mutex g_mem_mu;
+DevAllocator g_mem{nullptr, nullptr, nullptr};
+}  // namespace
+
+DevAllocator fdtdb::current_allocator() {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    return g_mem;
+}
+
+hipError_t fdtdb::dev_alloc(const DevAllocator &a, void **p, size_t bytes) {
+    if (!a.alloc) return hipMalloc(p, bytes);
+    *p = a.alloc(bytes, a.ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    if (reinterpret_cast<uintptr_t>(*p) % 256 != 0) {   // the kernels' vector accesses assume it
+        a.free(*p, a.ctx);
+        *p = nullptr;
+        return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+void fdtdb::dev_free(const DevAllocator &a, void *p) {
+    if (!p) return;
+    if (a.free) a.free(p, a.ctx);
+    else (void)hipFree(p);
+}
+
 // ---------------------------------------------------------------------------- checkpoint
 namespace {
 
@@ -934,6 +965,13 @@ extern "C" {
 const char *fdtdb_last_error(void) { return g_err.c_str(); }
 const char *fdtdb_version(void) { return "fdtdb 0.1 (gfx950)"; }
 
+fdtdb_status fdtdb_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(FDTDB_E_INVALID, "allocator needs both alloc and free");
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem = DevAllocator{alloc, free_fn, alloc ? ctx : nullptr};
+    return FDTDB_OK;
+}
+
 fdtdb_status fdtdb_create_grid(const fdtdb_grid_desc *d, fdtdb_grid *out) {
     if (!d || !out) return fail(FDTDB_E_INVALID, "null argument");
     *out = nullptr;
@@ -998,7 +1036,7 @@ fdtdb_status fdtdb_destroy_grid(fdtdb_grid g) {
     if (g->graph) (void)hipGraphExecDestroy(g->graph);
     for (auto &p : g->pending) { g->pool.push_back(p.a); g->pool.push_back(p.b); }
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
-    for (void *p : g->allocs) (void)hipFree(p);
+    for (void *p : g->allocs) dev_free(g->mem, p);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
     return FDTDB_OK;

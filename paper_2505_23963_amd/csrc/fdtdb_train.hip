@@ -540,10 +540,11 @@ struct fdtdb_trainer_s {
     long long adam_t = 0;
     bool loaded = false, have_w = false;
 
+    DevAllocator mem = current_allocator();
     fdtdb_status alloc(void **p, size_t bytes) {
         if (bytes == 0) bytes = 8;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) return tfail(FDTDB_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        hipError_t e = dev_alloc(mem, p, bytes);
+        if (e != hipSuccess) return tfail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
         allocs.push_back(*p);
         return FDTDB_OK;
     }
@@ -653,7 +654,7 @@ fdtdb_status fdtdb_trainer_destroy(fdtdb_trainer t) {
     if (!t) return FDTDB_OK;
     if (t->stream) (void)hipStreamSynchronize(t->stream);
     else (void)hipDeviceSynchronize();
-    for (void *p : t->allocs) (void)hipFree(p);
+    for (void *p : t->allocs) dev_free(t->mem, p);
     delete t;
     return FDTDB_OK;
 }

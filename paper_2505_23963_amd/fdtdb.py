@@ -71,6 +71,7 @@ SIGNATURES = [
     ("fdtdb_synchronize", C.c_int, [C.c_void_p]),
     ("fdtdb_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("fdtdb_set_graph", C.c_int, [C.c_void_p, C.c_int]),
+    ("fdtdb_set_allocator", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("fdtdb_save_state", C.c_int, [C.c_void_p, C.c_char_p]),
     ("fdtdb_load_state", C.c_int, [C.c_void_p, C.c_char_p]),
     ("fdtdb_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp, _dp]),
@@ -132,6 +133,36 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator_refs = []   # callback objects of every allocator ever set (objects may outlive a reset)
+
+
+def set_allocator(alloc=None, free=None):
+    """Device memory source of grids, batches and trainers created from now on (fdtdb_set_allocator):
+    alloc(nbytes) -> device address (int, 0 on failure), free(address).  No arguments: hipMalloc."""
+    if alloc is None and free is None:
+        _check(lib().fdtdb_set_allocator(None, None, None))
+        return
+    fa = _ALLOC_FN(lambda n, ctx: alloc(n) or None)
+    ff = _FREE_FN(lambda p, ctx: free(p))
+    _allocator_refs.append((fa, ff))
+    _check(lib().fdtdb_set_allocator(C.cast(fa, C.c_void_p), C.cast(ff, C.c_void_p), None))
+
+
+def torch_allocator(device: int = 0):
+    """alloc / free callables backed by PyTorch's caching allocator on one device."""
+    import torch
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(int(n), device)
+
+    def free(p):
+        torch.cuda.caching_allocator_delete(p)
+
+    return alloc, free
 
 
 def _check(st: int):

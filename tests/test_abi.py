@@ -140,3 +140,13 @@ def test_checkpoint_entry_points_reject_null_arguments(libfdtdb):
     for fn in (L.fdtdb_save_state, L.fdtdb_load_state):
         assert fn(None, b"/tmp/x.state") == -1
         assert b"null" in L.fdtdb_last_error()
+
+
+def test_allocator_hook_host_checks(libfdtdb):
+    """fdtdb_set_allocator needs both callbacks or neither; it touches no device."""
+    from paper_2505_23963_amd import lib
+    L = lib()
+    fa = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)(lambda n, c: None)
+    assert L.fdtdb_set_allocator(ctypes.cast(fa, ctypes.c_void_p), None, None) == -1
+    assert b"both" in L.fdtdb_last_error()
+    assert L.fdtdb_set_allocator(None, None, None) == 0
