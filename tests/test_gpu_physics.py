@@ -1,7 +1,11 @@
-"""The 1D Fabry-Perot cavity of the Appendix on the GPU (FP64): transmission spectra of the cavity
-filled with the plain Lorentz slab and with Lorentz-Bath slabs (Lorentzian and uniform bath forms of
-Table 1), against the oracle, and the behaviour Sec. IV.B reports at the larger coupling: the
-Lorentz-Bath polaritons transmit far more than the Lorentz ones, with the same Rabi splitting.
+"""The 1D simulations of Sec. IV on the GPU (FP64), with the parameters of the Appendix: the
+free-space slab spectra (Sec. IV.A: a uniform bath reproduces the Lorentz line, a Lorentzian bath
+gives a more Gaussian-like line with suppressed tails); the Fabry-Perot cavity filled with the plain
+Lorentz slab and with Lorentz-Bath slabs (Lorentzian and uniform bath forms of Table 1), against the
+oracle, and the behaviour Sec. IV.B reports: at the smaller coupling the two models give nearly the
+same spectra, with the bare cavity modes and an LP/UP pair; at the larger coupling the Lorentz-Bath
+polaritons transmit far more and live longer, with the same Rabi splitting; and the 2D cavity, periodic
+along y, gives the 1D spectrum (Sec. IV.C).
 
 Parameters (Appendix, angular units c / dx with dx = 0.01 um): n = 10 mirrors 0.02 um thick, 1 um
 apart, slab filling the cavity, nu0 = 1 um^-1, sigma = 0.02; Lorentz gamma / 2 pi = 0.04; bath
@@ -12,7 +16,7 @@ in for the paper's 100.
 import numpy as np
 import pytest
 
-from fdtdb_inputs.problem import PERIODIC, PML, DftFlux, Drude, LorentzBath, Problem, Source, box
+from fdtdb_inputs.problem import PERIODIC, PML, DftFlux, Drude, EnergyMonitor, LorentzBath, Problem, Source, box
 
 pytestmark = pytest.mark.gpu
 
@@ -39,11 +43,12 @@ def problem(slab):
     return p
 
 
-def slabs(sig=0.02):
+def slabs(sig=0.02, where=None):
     G = nu2w(0.04)
-    out = {"lorentz": LorentzBath(box((M0, M0 + D)), omega0=nu2w(1.0), gamma0=G, eps_inf=1.0, sigma=sig)}
+    b = box((M0, M0 + D)) if where is None else where
+    out = {"lorentz": LorentzBath(b, omega0=nu2w(1.0), gamma0=G, eps_inf=1.0, sigma=sig)}
     for form in ("lorentzian", "uniform"):
-        out[form] = LorentzBath(box((M0, M0 + D)), omega0=nu2w(1.0), gamma0=nu2w(0.0004), eps_inf=1.0, sigma=sig,
+        out[form] = LorentzBath(b, omega0=nu2w(1.0), gamma0=nu2w(0.0004), eps_inf=1.0, sigma=sig,
                                 n_bath=64, form=form, width=10 * G, bath_gamma=nu2w(0.0004), dephasing=0.99 * G)
     return out
 
@@ -75,3 +80,132 @@ def test_fabry_perot_lorentz_bath_vs_lorentz(oracle_lib):
     c_lo = np.sum(NU[lo] * v[lo]) / np.sum(v[lo])
     c_up = np.sum(NU[up] * v[up]) / np.sum(v[up])
     assert abs((c_up - c_lo) - np.sqrt(0.02)) < 0.1 * np.sqrt(0.02), (c_lo, c_up)
+
+
+# ----------------------------------------------------------------------------------- free space
+def _slab_problem(slab, steps):
+    """6 um cell (600 cells), 0.5 um CPML at both ends, 1 um slab at the centre, pulse at the left end."""
+    p = Problem(name="slab-free-space", ndim=1, n=(N, 1, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(50, 0, 0),
+                dtype="f64", steps=steps)
+    if slab is not None:
+        p.materials.append(slab)
+    p.sources.append(Source(comp=2, box=box((60, 61)), omega_c=nu2w(1.0), width=nu2w(1.2)))
+    p.dfts.append(DftFlux(0, box((N - 60, N - 59)), nu2w(NU_SLAB)))
+    return p
+
+
+NU_SLAB = np.linspace(0.8, 1.2, 401)
+
+
+def _run_flux(p, steps):
+    from paper_2505_23963_amd import Grid
+    print(f"[gpu] {p.name} {len(p.materials)} materials, {steps} steps", flush=True)
+    g = Grid(p, graph_chunk=128)
+    g.step(steps)
+    return g
+
+
+def test_free_space_slab_spectra():
+    """Sec. IV.A: sigma = 5e-3 slab; uniform bath ~ Lorentz line, Lorentzian bath suppresses the tails.
+    12 000 steps, before the discrete bath's recurrence at 2 pi / d_omega (31 500 steps)."""
+    steps = 12000
+    empty = _run_flux(_slab_problem(None, steps), steps).flux(0)
+    T = {k: _run_flux(_slab_problem(s, steps), steps).flux(0) / empty
+         for k, s in slabs(5e-3, box((250, 350))).items()}
+    A = {k: 1.0 - v for k, v in T.items()}
+    det = (NU_SLAB - 1.0) / 0.04          # detuning in units of the Lorentz linewidth
+    at = lambda k, x: A[k][np.argmin(np.abs(det - x))]
+    print("[gpu] absorption at 0, +-3 gamma:", {k: (round(at(k, 0), 4), round(at(k, -3), 4), round(at(k, 3), 4))
+                                                 for k in A}, flush=True)
+    depth = A["lorentz"].max()
+    assert 0.4 < depth < 0.7
+    # uniform bath: the Lorentz line within a few per cent of the dip depth, the same width
+    assert np.max(np.abs(T["uniform"] - T["lorentz"])) < 0.1 * depth
+    fwhm = {k: np.ptp(NU_SLAB[A[k] >= A[k].max() / 2]) for k in A}
+    assert abs(fwhm["uniform"] / fwhm["lorentz"] - 1) < 0.15, fwhm
+    # Lorentzian bath: same peak absorption, tails three linewidths out suppressed several-fold
+    assert abs(at("lorentzian", 0) / at("lorentz", 0) - 1) < 0.1
+    for x in (-3, 3):
+        assert at("lorentzian", x) < 0.3 * at("lorentz", x), x
+
+
+# ------------------------------------------------------------------------------ cavity, weaker
+def test_fabry_perot_weak_coupling_models_agree():
+    """Sec. IV.B at sigma = 2e-3: bare cavity modes near nu = 0.5 and 1.5, an LP/UP pair split by about
+    omega0 sqrt(sigma) around 1.0, and the Lorentz and Lorentz-Bath(L) spectra nearly the same.
+    30 000 steps, before the discrete bath's recurrence."""
+    steps = 30000
+    nu = np.linspace(0.4, 1.6, 1201)
+
+    def run(slab):
+        p = problem(slab)
+        p.dfts[0] = DftFlux(0, box((N - 150, N - 149)), nu2w(nu))
+        return _run_flux(p, steps).flux(0)
+
+    empty = run(None)
+    sl = slabs(2e-3)
+    T = {k: run(sl[k]) / empty for k in ("lorentz", "lorentzian")}
+    for k, v in T.items():
+        for centre, lo, hi in ((0.5, 0.45, 0.6), (1.5, 1.4, 1.6)):
+            w = (nu > lo) & (nu < hi)
+            i = np.argmax(v[w])
+            assert v[w][i] > 0.7 and abs(nu[w][i] - centre) < 0.05, (k, centre, nu[w][i], v[w][i])
+    lo, up = (nu > 0.9) & (nu < 1.0), (nu > 1.0) & (nu < 1.1)
+    v = T["lorentz"]
+    split = nu[up][np.argmax(v[up])] - nu[lo][np.argmax(v[lo])]
+    assert abs(split - np.sqrt(2e-3)) < 0.15 * np.sqrt(2e-3), split
+    # nearly the same polaritons: peak heights within a quarter, transmitted weight within 15 %
+    # (at sigma = 2e-2 the Lorentz-Bath(L) peaks are twenty times the Lorentz ones)
+    b = T["lorentzian"]
+    for sel in (lo, up):
+        assert abs(b[sel].max() / v[sel].max() - 1) < 0.25, (b[sel].max(), v[sel].max())
+    win = lo | up
+    ia, ib = np.trapezoid(v[win], nu[win]), np.trapezoid(b[win], nu[win])
+    assert abs(ib / ia - 1) < 0.15, (ia, ib)
+
+
+# ---------------------------------------------------------------------- in-cavity EM energy
+def test_cavity_energy_lives_longer_with_bath():
+    """Sec. IV.B (in-cavity energy under a broadband pulse launched inside the cavity), sigma = 2e-2:
+    the EM energy between the mirrors decays more slowly with the Lorentz-Bath(L) slab."""
+    steps = 8000
+    E = {}
+    for k in ("lorentz", "lorentzian"):
+        p = problem(slabs()[k])
+        p.sources[0] = Source(comp=2, box=box((260, 261)), omega_c=nu2w(1.0), width=nu2w(1.2))
+        p.energies.append(EnergyMonitor(box((M0, M0 + D)), every=50))
+        E[k] = _run_flux(p, steps).energy(0)[:, 0]
+    at = lambda k, s: E[k][s // 50]
+    print("[gpu] in-cavity EM energy:", {k: [round(float(at(k, s)), 4) for s in (1000, 3000, 5000, 7950)] for k in E},
+          flush=True)
+    assert abs(at("lorentzian", 200) / at("lorentz", 200) - 1) < 0.01       # same pulse, same start
+    # after the pulse the energy beats between polaritons and bare modes: compare its mean and its
+    # fitted exponential decay rate over steps [3000, 8000)
+    t = np.arange(len(E["lorentz"])) * 50
+    w = (t >= 3000) & (t < 8000)
+    mean = {k: E[k][w].mean() for k in E}
+    rate = {k: -np.polyfit(t[w], np.log(E[k][w]), 1)[0] for k in E}
+    print("[gpu] mean, decay rate per step:", {k: (round(float(mean[k]), 4), float(rate[k])) for k in E}, flush=True)
+    assert mean["lorentzian"] > 1.15 * mean["lorentz"]
+    assert rate["lorentzian"] < 0.95 * rate["lorentz"]
+
+
+# ------------------------------------------------------------------------------------ 2D = 1D
+def test_2d_cavity_equals_1d():
+    """Sec. IV.C: the cavity periodic along y, driven by a source line over all y, gives the 1D
+    spectrum (per unit length along y) to FP64 rounding."""
+    steps = 6000
+    nu = np.linspace(0.6, 1.4, 161)
+    p1 = problem(slabs()["lorentzian"])
+    p1.dfts[0] = DftFlux(0, box((N - 150, N - 149)), nu2w(nu))
+    f1 = _run_flux(p1, steps).flux(0)
+    ny = 4
+    p2 = Problem(name="fp-2d", ndim=2, n=(N, ny, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(40, 0, 0),
+                 dtype="f64", steps=steps)
+    for m in p1.materials:
+        m2 = m.__class__(**{**m.__dict__, "box": box((m.box[0][0], m.box[1][0]), (0, ny))})
+        p2.materials.append(m2)
+    p2.sources.append(Source(comp=2, box=box((100, 101), (0, ny)), omega_c=nu2w(1.0), width=nu2w(1.2)))
+    p2.dfts.append(DftFlux(0, box((N - 150, N - 149), (0, ny)), nu2w(nu)))
+    f2 = _run_flux(p2, steps).flux(0) / ny
+    assert np.max(np.abs(f2 - f1)) <= 1e-10 * np.max(np.abs(f1))
