@@ -498,11 +498,12 @@ template <int DIM, typename T, int NG, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const BathCoef<NG> cf) {
     using V4 = nvec4_t<T>;
     constexpr int NC = DIM == 3 ? 3 : 1;
-    // blocks in launch order: every XCD streams next to the others (one front through the bath
-    // arrays); giving each XCD a contiguous eighth, as the other kernels do, measured 1.8 % slower
-    // here (1.73 against 1.70 ms on the 256 x 256 x 400 layer), the H-neighbour reuse it buys being
-    // small next to this kernel's 364 bytes per cell
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    // block order: with few bath streams (components x groups <= 6) blocks go in launch order, every
+    // XCD streaming next to the others; with more, each XCD takes a contiguous eighth of the layer.
+    // Measured per launch: 3D N_b = 8 (3 x 2 groups) 1.69 ms in launch order against 1.73 ms; 2D
+    // N_b = 64 (1 x 16) 0.191 against 0.156 ms; 3D N_b = 16 (3 x 4) equal within noise.
+    constexpr bool kLaunchOrder = NC * NG <= 6;
+    const int t = (kLaunchOrder ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x;
     const bool live = t < a.ext[0] * a.ext12;
     double ef = 0.0, ep = 0.0, eb = 0.0;
     bool sample = false;
