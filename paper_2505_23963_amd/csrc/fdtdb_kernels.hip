@@ -614,6 +614,75 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
 }
 
 // ---------------------------------------------------------------------------------------------
+// Lorentz-Bath E update, one (component, cell) per thread: the same arithmetic as the load-first
+// kernel above, for 3D baths whose three components' levels do not fit one thread's registers at
+// a useful occupancy (components x groups > 6).  Blocks are component-major, so the waves of a
+// block stream one component's arrays; within a component each XCD takes a contiguous share.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int NG, int C>
+__device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG> &cf, int t) {
+    using V4 = nvec4_t<T>;
+    int i, j, k;
+    unflatten<3>(t, a.lo, a.ext, a.ext12, i, j, k);
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const int coord[3] = {i, j, k};
+    const int stride[3] = {s0, s1, 1};
+    const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+    const int mcells = (int)a.mcells;
+    constexpr int a1 = curl_a1(C), a2 = curl_a2(C);
+    const bool has_sig = a.sigma != nullptr;
+    const T *sp = has_sig ? static_cast<const T *>(a.sigma) + m : static_cast<const T *>(a.E[C]) + q;
+    const T sig_raw = *sp;
+    const double t1 = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+    const double t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+    const double Eo = (double)static_cast<const T *>(a.E[C])[q];
+    const double Pc = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pcur[C]) + m);
+    const double Pp = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pnew[C]) + m);
+    const V4 *Yc = static_cast<const V4 *>(a.Ycur[C]);
+    V4 *Yn = static_cast<V4 *>(a.Ynew[C]);
+    V4 yc[NG], yp[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        yc[g] = __builtin_nontemporal_load(Yc + (long long)g * mcells + m);
+        yp[g] = __builtin_nontemporal_load(Yn + (long long)g * mcells + m);
+    }
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    const double sig = has_sig ? (double)sig_raw : a.sigma0;
+    const double En = Eo + a.inv_eps * (a.dt * (t1 - t2) - (Pc - Pp)) - source_term(a, amp, C, i, j, k);
+    double S = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) S += cf.md[4 * g + u][3] * (double)yc[g][u] + cf.md[4 * g + u][4] * (double)yp[g][u];
+    }
+    const double Pnew = cf.head[0] * sig * En - cf.head[1] * Pc - cf.head[2] * Pp - S;
+    const double dP = Pnew - Pp;
+    static_cast<T *>(a.E[C])[q] = (T)En;
+    __builtin_nontemporal_store((T)Pnew, static_cast<T *>(a.Pnew[C]) + m);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        V4 o;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            o[u] = (T)(cf.md[4 * g + u][0] * (double)yc[g][u] + cf.md[4 * g + u][1] * (double)yp[g][u] + cf.md[4 * g + u][2] * dP);
+        __builtin_nontemporal_store(o, Yn + (long long)g * mcells + m);
+    }
+}
+
+template <typename T, int NG>
+__global__ __launch_bounds__(kBlock) void k_update_e_bath_c(const EArgs a, const BathCoef<NG> cf) {
+    const int nbc = gridDim.x / 3;                  // blocks per component
+    const int c = blockIdx.x / nbc;
+    const int t = xcd_block(blockIdx.x - c * nbc, nbc) * kBlock + threadIdx.x;
+    if (t >= a.ext[0] * a.ext12) return;
+    if (c == 0) bath_component<T, NG, 0>(a, cf, t);
+    else if (c == 1) bath_component<T, NG, 1>(a, cf, t);
+    else bath_component<T, NG, 2>(a, cf, t);
+}
+
+// ---------------------------------------------------------------------------------------------
 // H update, generic form
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, bool PML>
@@ -1240,6 +1309,8 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
             for (int u = 0; u < 5; ++u) cf.md[j][u] = coef_host[kCoefHead + j * kCoefMode + u];
         if (energy)
             hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
+        else if constexpr (DIM == 3 && NC * NG > 6)
+            hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * nblocks(n)), dim3(kBlock), 0, s, a, cf);
         else
             hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
         return hipGetLastError();

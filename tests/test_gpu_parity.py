@@ -300,3 +300,52 @@ def test_cpml_layers_fp64(oracle_lib, p):
     errs = rel_fields(g, o, fields_of(p))
     print("rel-L2 per component:", errs, flush=True)
     assert max(errs.values()) < 1e-12, errs
+
+
+# ------------------------------------------------------------------- 3D baths of more than 8 modes
+@pytest.mark.parametrize("case,dtype,tol", [("config5", "f64", 1e-12), ("config5", "f32", 1e-5),
+                                            ("config2_nb12", "f32", 1e-5)])
+def test_3d_large_baths_component_split(oracle_lib, case, dtype, tol):
+    """3D baths whose components x mode groups exceed 6 take the one-(component, cell)-per-thread kernel:
+    the 512^3 layout (N_b = 16, Gaussian-profile plane source) on an 8 x 8 crop, and the planar cavity
+    with N_b = 12, against the oracle."""
+    if case == "config5":
+        p = configs.config5_3d_large(nx=8, ny=8, steps=500, nfreq=32, dtype=dtype)
+    else:
+        p = configs.config2_3d(nx=10, ny=12, steps=220, nfreq=64, nb=12, dtype=dtype)
+    g, o = run_pair(oracle_lib, p)
+    # the Gaussian-profile source drives E_y, E_z, H_x and H_z only through diffraction (1e-8 to 1e-3
+    # of the dominant norm).  FP64: components below 1 % of the largest are measured against 1 % of it.
+    # FP32: against the largest itself, since a component formed by cancellation between transverse
+    # differences of the large ones carries their FP32 storage rounding (4e-5 of E_z's own norm is
+    # 3e-8 of the field's scale)
+    floor = 1e-2 if dtype == "f64" else 1.0
+    ref = {c: o.field(c) for c in range(6)}
+    big = max(np.linalg.norm(v) for v in ref.values())
+    errs = {c: np.linalg.norm(g.field(c) - ref[c]) / max(np.linalg.norm(ref[c]), floor * big) for c in range(6)}
+    print("rel-L2 per component:", errs, flush=True)
+    assert max(errs.values()) < tol, errs
+    assert rel(g.flux(0), o.flux(0)) < tol
+    mi = 0 if case == "config5" else 1
+    for get, t in ((lambda x, c: x.polarization(mi, c, 0), tol), (lambda x, c: x.bath(mi, c, 1), 10 * tol)):
+        r = [get(o, c) for c in range(3)]
+        top = max(np.linalg.norm(v) for v in r)
+        for c in range(3):
+            e = np.linalg.norm(get(g, c) - r[c]) / max(np.linalg.norm(r[c]), floor * top)
+            assert e < t, (c, e)
+
+
+def test_component_split_bitwise_equals_per_cell_kernel():
+    """The component-split kernel and the per-cell kernel (taken when an energy monitor samples the
+    region) advance the N_b = 16 layer identically, bit for bit."""
+    from paper_2505_23963_amd import Grid
+    p = configs.config5_3d_large(nx=8, ny=8, steps=300, nfreq=8, dtype="f32")
+    q = configs.config5_3d_large(nx=8, ny=8, steps=300, nfreq=8, dtype="f32")
+    q.energies.append(EnergyMonitor(box((0, 8), (0, 8), (140, 370)), every=1))
+    a, b = Grid(p), Grid(q)
+    a.step(300)
+    b.step(300)
+    for c in range(6):
+        assert np.array_equal(a.field(c), b.field(c)), c
+    for c in range(3):
+        assert np.array_equal(a.bath(0, c, 0), b.bath(0, c, 0)), c
