@@ -748,12 +748,15 @@ __device__ __forceinline__ const RegionDesc &v4_region(const A &a, Cell4 &c) {
     for (int s = 0; s < kMaxGroup; ++s) r += b >= a.rd->block0[s];
     const RegionDesc &D = a.rd->d[r];
     const int t = (b - a.rd->block0[r]) * kBlock + threadIdx.x;
-    const int ext2q = D.ext[2] >> 2;
+    // the region's z range rounded out to whole 4-cell groups (a region that is not 4-aligned leaves
+    // its edge groups partly outside; the kernels store only the cells inside)
+    const int base = D.lo[2] & ~3;
+    const int ext2q = ((D.lo[2] + D.ext[2] + 3) >> 2) - (D.lo[2] >> 2);
     c.live = t < D.ext[0] * D.ext[1] * ext2q;
     const int rr = t / ext2q;
     const int kq = t - rr * ext2q;
     const int r2 = rr / D.ext[1];
-    c.k = D.lo[2] + 4 * kq;
+    c.k = base + 4 * kq;
     c.i = D.lo[0] + r2;
     c.j = D.lo[1] + (rr - r2 * D.ext[1]);
     c.tc = 4 * t;
@@ -1141,9 +1144,21 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
         wy[e] = (T)oy[e];
         wz[e] = (T)oz[e];
     }
-    __builtin_nontemporal_store(wx, Ex);
-    __builtin_nontemporal_store(wy, Ey);
-    __builtin_nontemporal_store(wz, Ez);
+    const int klo = D.lo[2], khi = D.lo[2] + D.ext[2];
+    if (k >= klo && k + 4 <= khi) {
+        __builtin_nontemporal_store(wx, Ex);
+        __builtin_nontemporal_store(wy, Ey);
+        __builtin_nontemporal_store(wz, Ez);
+    } else {   // edge group of a region that is not 4-aligned (background cells only): own cells only
+        T *ex_ = static_cast<T *>(a.E[0]) + q, *ey_ = static_cast<T *>(a.E[1]) + q, *ez_ = static_cast<T *>(a.E[2]) + q;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (k + e >= klo && k + e < khi) {
+                ex_[e] = wx[e];
+                ey_[e] = wy[e];
+                ez_[e] = wz[e];
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------------------------

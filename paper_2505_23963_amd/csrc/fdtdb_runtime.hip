@@ -499,7 +499,16 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     for (auto &r : g->regions)
         for (auto &e : g->ens)
             if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
-    auto blocks_of = [](const Region &r, bool v4) { return ((v4 ? r.cells() / 4 : r.cells()) + kBlock - 1) / kBlock; };
+    // threads of a region: one per cell, or (vector kernels) one per 4-cell group of the region's
+    // fastest-axis range rounded out to whole groups
+    auto blocks_of = [&](const Region &r, bool v4) {
+        long long n = r.cells();
+        if (v4) {
+            const int a = g->ndim == 3 ? 2 : 1;
+            n = n / (r.hi[a] - r.lo[a]) * (((r.hi[a] + 3) >> 2) - (r.lo[a] >> 2));
+        }
+        return (n + kBlock - 1) / kBlock;
+    };
     auto make = [&](std::vector<Launch> &out, const std::vector<Region> &rs, const std::vector<int> &idx, bool group,
                     bool v4) {
         for (size_t s = 0; s < idx.size();) {
@@ -524,6 +533,11 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         if (g->ndim == 2) return rg.lo[1] % 4 == 0 && (rg.hi[1] - rg.lo[1]) % 4 == 0 && g->n[1] % 4 == 0;
         return g->ndim == 3 && rg.lo[2] % 4 == 0 && (rg.hi[2] - rg.lo[2]) % 4 == 0 && g->n[2] % 4 == 0;
     };
+    // 3D background regions without CPML terms may take the vector kernel unaligned: it computes
+    // whole 4-cell groups and stores only the region's own cells at the edges
+    auto bg_unaligned4 = [&](const Region &rg) {
+        return g->ndim == 3 && g->n[2] % 4 == 0 && rg.mat < 0 && rg.pml_mask == 0;
+    };
     {
         std::vector<int> bg4, bg, solo, drude4;
         for (int i = 0; i < (int)g->regions.size(); i++) {
@@ -532,7 +546,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
                 const Material &mt = g->mats[rg.mat];
                 const bool m4 = mt.mext[2] % 4 == 0 && (rg.lo[2] - (int)mt.lo[2]) % 4 == 0;
                 (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy ? drude4 : solo).push_back(i);
-            } else if (z4(rg) && !rg.energy) {
+            } else if ((z4(rg) || bg_unaligned4(rg)) && !rg.energy) {
                 bg4.push_back(i);
             } else {
                 bg.push_back(i);
