@@ -18,19 +18,41 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *srcs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in proc.stdout.splitlines() if "packed-fp32-ops" not in l)
-    if proc.returncode != 0:
+    return proc.returncode, out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel (one hipcc per file), then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build", f"obj{os.getpid()}")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for s in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
+        jobs.append((obj, [hipcc, *compile_flags, "-c", "-o", obj, os.path.join(CSRC, s)]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: _run(j[1], verbose), jobs))
+    for (rc, out), (obj, _) in zip(results, jobs):
+        if rc != 0:
+            sys.stderr.write(out + "\n")
+            raise RuntimeError(f"hipcc failed compiling {os.path.basename(obj)}")
+    tmp = LIB + f".tmp{os.getpid()}"
+    rc, out = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *(o for o, _ in jobs)], verbose)
+    if rc != 0:
         sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed building libfdtdb.so")
+        raise RuntimeError("hipcc failed linking libfdtdb.so")
     os.replace(tmp, LIB)
+    for o, _ in jobs:
+        os.remove(o)
+    os.rmdir(objdir)
     return LIB
 
 

@@ -126,6 +126,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2505_23963_amd.build)")
+        # PyTorch ships its own HIP runtime under the same soname as the system one this library links;
+        # the first loaded serves the whole process, and PyTorch cannot start its GPU support on a runtime
+        # loaded before it.  Loading PyTorch first keeps one runtime that both use (streams and the
+        # caching allocator are shared with it).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)
