@@ -9,8 +9,9 @@ register arithmetic and FP64 DFT accumulators.
 
 One step = the whole time step: clock/source, every region's E and material
 update (Lorentz-Bath bath force, polarization and bath modes), every region's
-H update (CPML included), DFT staging, and the blocked DFT flush (every 32
-steps; the timed step count is a multiple of 32 so flushes are included).
+H update (CPML included), DFT staging, and the blocked DFT flush (every 64
+steps; the default 64 timed steps include one flush, so its cost is spread
+over the steps as in a long run).
 
 Prints one JSON line.  `value` is cell-updates per second (Gcell-updates/s)
 over the timed steps with all state resident in HBM.  `roofline` is the
