@@ -199,7 +199,7 @@ fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps);
  * source clock).  save_state synchronizes the stream and writes one binary file (host path,
  * overwritten; nothing of the caller's is retained).  load_state reads such a file into a grid
  * built with the same set-up (geometry, dtype, materials and their parameters, sources,
- * monitors, probes; the closure weights themselves are not compared), after which stepping
+ * monitors, probes; per-cell sigma values and closure weights are not compared), after which stepping
  * continues exactly as the saved grid would have: a resumed run equals an uninterrupted one
  * bitwise.  Errors: E_INVALID for null arguments or a file that cannot be opened or written;
  * E_STATE for a file that is not a state file, is truncated, or was written by a grid with
