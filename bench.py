@@ -236,7 +236,8 @@ def bench_closure2d(args):
     cells = np.arange(256 * 256)
     t0 = time.perf_counter()
     E, P = closure.record(rec, 0, 2, cells, 1024, stream=s)
-    res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), stream=s)
+    res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), epochs=args.train_epochs,
+                        stream=s)
     t_train = time.perf_counter() - t0
     # multiply-adds per window-step: forward 1408, backward 1312, weight gradients 1477
     train_flops = 2.0 * (1408 + 1312 + 1477) * len(cells) * 1024 * len(res["curve"])
@@ -266,7 +267,7 @@ def bench_closure2d(args):
     v_cl, ms_cl, k_cl, _ = timed(cl)
     # accuracy over the workload's 10000 steps (and before the explicit bath's revival)
     out_err = {}
-    for horizon in (2500, 10000):
+    for horizon in (() if args.skip_accuracy else (2500, 10000)):
         fe = Grid(p, stream=s)
         fe.step(horizon)
         ref_f, ref_e = fe.flux(0), fe.field(2)
@@ -389,6 +390,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--train-epochs", type=int, default=600,
+                    help="closure training epochs (closure2d; fewer only to profile the inference kernels)")
+    ap.add_argument("--skip-accuracy", action="store_true",
+                    help="closure2d: skip the accuracy runs against the explicit bath (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from", default=None,
