@@ -841,8 +841,12 @@ __global__ __launch_bounds__(kBlock) void k_update_h3_v4(const HArgs a) {
     const V ex_y = *reinterpret_cast<const V *>(Ex + qy);
     const V ey_x = *reinterpret_cast<const V *>(Ey + qx);
     const V ez_x = *reinterpret_cast<const V *>(Ez + qx);
-    const double ex_z = okz ? (double)Ex[qz] : 0.0;
-    const double ey_z = okz ? (double)Ey[qz] : 0.0;
+    // E_x and E_y one cell beyond the group: the next lane's first values when that lane holds the
+    // row's next group (every lane but a row's or a wave's last), else a load
+    const T exs = __shfl_down(ex.x, 1), eys = __shfl_down(ey.x, 1);
+    const bool from_lane = (threadIdx.x & 63) < 63 && k + 4 < ((D.lo[2] + D.ext[2] + 3) & ~3);
+    const double ex_z = from_lane ? (double)exs : (okz ? (double)Ex[qz] : 0.0);
+    const double ey_z = from_lane ? (double)eys : (okz ? (double)Ey[qz] : 0.0);
     // H is read once and written once per step: streamed (non-temporal); E rows are shared with the
     // neighbouring threads and stay cacheable
     using NV = nvec4_t<T>;
@@ -1059,8 +1063,12 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     const V hx_y = *reinterpret_cast<const V *>(Hx + qy);
     const V hy_x = *reinterpret_cast<const V *>(Hy + qx);
     const V hz_x = *reinterpret_cast<const V *>(Hz + qx);
-    const double hx_z = okz ? (double)Hx[qz] : 0.0;
-    const double hy_z = okz ? (double)Hy[qz] : 0.0;
+    // H_x and H_y one cell before the group: the previous lane's last values when that lane holds
+    // the row's previous group, else a load
+    const T hxs = __shfl_up(hx.w, 1), hys = __shfl_up(hy.w, 1);
+    const bool from_lane = (threadIdx.x & 63) > 0 && k > (D.lo[2] & ~3);
+    const double hx_z = from_lane ? (double)hxs : (okz ? (double)Hx[qz] : 0.0);
+    const double hy_z = from_lane ? (double)hys : (okz ? (double)Hy[qz] : 0.0);
     // E is read once and written once per step: streamed (non-temporal); H rows are shared with the
     // neighbouring threads and stay cacheable
     using NV = nvec4_t<T>;
