@@ -45,7 +45,8 @@ def source_hash() -> str:
     h = hashlib.sha256()
     for start in ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
                   "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
-                  "__device__ __forceinline__ void unflatten(", "void k_update_e_bath(const EArgs a"):
+                  "__device__ __forceinline__ void unflatten(", "__device__ __forceinline__ double z_minus_lane(",
+                  "void k_update_e_bath(const EArgs a"):
         s = src.find(start)
         e = src.find("\n}\n", s)
         h.update(src[s:e].encode() if s >= 0 else start.encode())

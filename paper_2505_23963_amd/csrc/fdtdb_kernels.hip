@@ -53,6 +53,15 @@ __device__ __forceinline__ double at_minus(const void *f, int q, int coord, int 
     const double v = (double)static_cast<const T *>(f)[id];
     return ok ? v : 0.0;
 }
+// A field one cell below q along z, in a 3D kernel with one cell per thread and threads running
+// along z rows: the previous lane's own value when that lane holds cell k - 1 of the row (every lane
+// but a row's or a wave's first), else a load with the boundary rule of at_minus
+template <typename T>
+__device__ __forceinline__ double z_minus_lane(const void *f, T own, int q, int k, int klo, int n, int per) {
+    const T sv = __shfl_up(own, 1);
+    const bool from_lane = (threadIdx.x & 63) > 0 && k > klo;
+    return from_lane ? (double)sv : at_minus<T>(f, q, k, 1, n, per);
+}
 template <typename T>
 __device__ __forceinline__ double at_plus(const void *f, int q, int coord, int stride, int n, int per) {
     const bool in = coord < n - 1;
@@ -533,10 +542,19 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
             const int a1 = curl_a1(c), a2 = curl_a2(c);
             t1[ci] = 0.0;
             t2[ci] = 0.0;
-            if (axis_live(DIM, a1) && h_active(DIM, a2))
-                t1[ci] = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
-            if (axis_live(DIM, a2) && h_active(DIM, a1))
-                t2[ci] = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+            // in 3D the z neighbour comes from the previous lane (threads run along z rows of the box)
+            if (axis_live(DIM, a1) && h_active(DIM, a2)) {
+                const T own = static_cast<const T *>(a.H[a2])[q];
+                t1[ci] = (double)own - (DIM == 3 && a1 == 2
+                                            ? z_minus_lane<T>(a.H[a2], own, q, k, a.lo[2], a.n[2], a.per[2])
+                                            : at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]));
+            }
+            if (axis_live(DIM, a2) && h_active(DIM, a1)) {
+                const T own = static_cast<const T *>(a.H[a1])[q];
+                t2[ci] = (double)own - (DIM == 3 && a2 == 2
+                                            ? z_minus_lane<T>(a.H[a1], own, q, k, a.lo[2], a.n[2], a.per[2])
+                                            : at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]));
+            }
             Eo[ci] = (double)static_cast<const T *>(a.E[c])[q];
             // polarization and bath levels are read once and written once per step: stream them
             Pc[ci] = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pcur[c]) + m);
