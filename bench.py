@@ -46,6 +46,7 @@ def source_hash() -> str:
     for start in ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
                   "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
                   "__device__ __forceinline__ void unflatten(", "__device__ __forceinline__ double z_minus_lane(",
+                  "__device__ __forceinline__ double minus_lane_pairs(", "__host__ __device__ inline long long pair_threads(",
                   "void k_update_e_bath(const EArgs a"):
         s = src.find(start)
         e = src.find("\n}\n", s)

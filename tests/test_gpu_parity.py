@@ -118,6 +118,26 @@ def test_3d_all_components_closed_box(oracle_lib):
     assert max(errs.values()) < 1e-12, errs
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_3d_bath_layer_ragged_rows_and_chunks(oracle_lib, dtype, tol):
+    """A Lorentz-Bath block whose rows do not fill the 3D kernel's waves: an odd number of y rows (the
+    last wave's upper half idle), a z extent of 75 (two full 32-cell chunks and a ragged one), and a
+    block starting at z = 0 on a periodic z axis (the z - 1 neighbour wraps round)."""
+    rng = np.random.default_rng(5)
+    n = (6, 9, 100)
+    p = Problem(name="ragged3d", ndim=3, n=n, bc=(CLOSED, PERIODIC, PERIODIC), dtype=dtype, steps=200)
+    w, gm, k = configs.ohmic_bath(8, 0.8, 1.2, 1.0, seed=13)
+    p.materials.append(LorentzBath(box((1, 5), (0, 9), (0, 75)), omega0=1.0, gamma0=0.01, eps_inf=1.2,
+                                   sigma_cells=rng.uniform(0.02, 0.1, 4 * 9 * 75), n_bath=8, omega_j=w,
+                                   gamma_j=gm, k_j=k))
+    p.sources += [Source(comp=0, box=box((2, 4), (1, 8), (80, 81)), omega_c=1.0, width=0.5),
+                  Source(comp=2, box=box((3, 4), (4, 5), (90, 91)), omega_c=0.9, width=0.5, amplitude=0.5)]
+    g, o = run_pair(oracle_lib, p)
+    errs = rel_fields(g, o, range(6))
+    assert max(errs.values()) < tol, errs
+    assert rel(g.bath(0, 0, 0), o.bath(0, 0, 0)) < tol
+
+
 # ------------------------------------------------------------------------------------------ 2D
 def test_config4_crop_explicit(oracle_lib):
     """2D TM grid with CPML on all sides and a Lorentzian-form bath patch (N_b = 64), FP32."""
