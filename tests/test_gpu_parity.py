@@ -118,17 +118,18 @@ def test_3d_all_components_closed_box(oracle_lib):
     assert max(errs.values()) < 1e-12, errs
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_3d_bath_layer_ragged_rows_and_chunks(oracle_lib, dtype, tol):
+@pytest.mark.parametrize("dtype,tol,nb", [("f64", 1e-12, 8), ("f32", 1e-5, 8), ("f64", 1e-12, 3)])
+def test_3d_bath_layer_ragged_rows_and_chunks(oracle_lib, dtype, tol, nb):
     """A Lorentz-Bath block whose rows do not fill the 3D kernel's waves: an odd number of y rows (the
     last wave's upper half idle), a z extent of 75 (two full 32-cell chunks and a ragged one), and a
-    block starting at z = 0 on a periodic z axis (the z - 1 neighbour wraps round)."""
+    block starting at z = 0 on a periodic z axis (the z - 1 neighbour wraps round); one and two groups
+    of four bath modes."""
     rng = np.random.default_rng(5)
     n = (6, 9, 100)
     p = Problem(name="ragged3d", ndim=3, n=n, bc=(CLOSED, PERIODIC, PERIODIC), dtype=dtype, steps=200)
-    w, gm, k = configs.ohmic_bath(8, 0.8, 1.2, 1.0, seed=13)
+    w, gm, k = configs.ohmic_bath(nb, 0.8, 1.2, 1.0, seed=13)
     p.materials.append(LorentzBath(box((1, 5), (0, 9), (0, 75)), omega0=1.0, gamma0=0.01, eps_inf=1.2,
-                                   sigma_cells=rng.uniform(0.02, 0.1, 4 * 9 * 75), n_bath=8, omega_j=w,
+                                   sigma_cells=rng.uniform(0.02, 0.1, 4 * 9 * 75), n_bath=nb, omega_j=w,
                                    gamma_j=gm, k_j=k))
     p.sources += [Source(comp=0, box=box((2, 4), (1, 8), (80, 81)), omega_c=1.0, width=0.5),
                   Source(comp=2, box=box((3, 4), (4, 5), (90, 91)), omega_c=0.9, width=0.5, amplitude=0.5)]
@@ -368,6 +369,24 @@ def test_3d_large_baths_component_split(oracle_lib, case, dtype, tol):
         for c in range(3):
             e = np.linalg.norm(get(g, c) - r[c]) / max(np.linalg.norm(r[c]), floor * top)
             assert e < t, (c, e)
+
+
+def test_two_row_waves_bitwise_equal_one_row_kernel():
+    """The 3D Lorentz-Bath kernel's two-row wave layout (taken without energy sampling) and its
+    one-row layout (taken when an energy monitor samples the layer) advance the N_b = 8 layer
+    identically, bit for bit, on a crop with an odd number of rows."""
+    from paper_2505_23963_amd import Grid
+    p = configs.config2_3d(nx=6, ny=7, steps=300, nfreq=8, dtype="f32")
+    q = configs.config2_3d(nx=6, ny=7, steps=300, nfreq=8, dtype="f32")
+    q.energies.append(EnergyMonitor(box((0, 6), (0, 7), (56, 456)), every=1))
+    a, b = Grid(p), Grid(q)
+    a.step(300)
+    b.step(300)
+    for c in range(6):
+        assert np.array_equal(a.field(c), b.field(c)), c
+    for c in range(3):
+        assert np.array_equal(a.polarization(1, c, 0), b.polarization(1, c, 0)), c
+        assert np.array_equal(a.bath(1, c, 0), b.bath(1, c, 0)), c
 
 
 def test_component_split_bitwise_equals_per_cell_kernel():
