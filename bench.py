@@ -251,7 +251,7 @@ def bench_closure2d(args):
         g = Grid(prob or p, stream=s, closures=closures)
         g.step(args.warmup)
         g.synchronize()
-        g.set_profiling(True, dispersive_only=True)
+        g.set_profiling(True, bath_only=True)
         g.kernel_records()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -341,7 +341,7 @@ def bench_large3d(args):
         g = Grid(p, stream=s, closures=closures)
         g.step(args.warmup)
         g.synchronize()
-        g.set_profiling(True, dispersive_only=True)
+        g.set_profiling(True, bath_only=True)
         g.kernel_records()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -443,7 +443,7 @@ def main():
     g.step(args.warmup)
     torch.cuda.synchronize()
     g.synchronize()
-    g.set_profiling(True, dispersive_only=True)   # events around the material launches only
+    g.set_profiling(True, bath_only=True)   # events around the bath launches only
     g.kernel_records()                       # start from empty event lists
     base = {(r["region"], r["phase"]): (r["ms_total"], r["launches"]) for r in g.kernel_records()}
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -497,7 +497,7 @@ def main():
         },
         "step_algorithmic_GBps": round(stats["bytes_per_step"] / (ms_step * 1e-3) / 1e9, 1),
         "step_algorithmic_bytes": stats["bytes_per_step"],
-        "dispersive_kernel_ms_per_step": round(kern_ms, 4),
+        "bath_kernel_ms_per_step": round(kern_ms, 4),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

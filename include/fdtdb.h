@@ -246,9 +246,10 @@ typedef struct {
 fdtdb_status fdtdb_get_stats(fdtdb_grid g, fdtdb_stats *out);
 
 /* Per-launch timing.  mode 1: fdtdb_step launches directly (no graph replay) and brackets every
- * E and H launch with HIP events on the grid's stream; mode 2: only the E launches of dispersive
- * materials (the launches that dominate a step) are bracketed, so the timing of the others is
- * not disturbed; 0: off.  fdtdb_kernel_records collects the events.  E_INVALID for other modes. */
+ * E and H launch with HIP events on the grid's stream; mode 2: only the E launches of Lorentz-Bath
+ * and learned-closure materials (the launches that dominate a step) are bracketed, so that the
+ * others run undisturbed (each bracketed launch adds roughly 7 us of event overhead to a step);
+ * 0: off.  fdtdb_kernel_records collects the events.  E_INVALID for other modes. */
 fdtdb_status fdtdb_set_profiling(fdtdb_grid g, int mode);
 
 typedef struct {

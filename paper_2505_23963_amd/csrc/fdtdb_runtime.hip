@@ -756,7 +756,7 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         a.block_base = L.block_base;
         const int rec = (int)(&L - &g->elaunch[0]);
         Pending pe{rec, nullptr, nullptr};
-        const bool ev = g->profiling == 1 || (g->profiling == 2 && kind != K_BACKGROUND);
+        const bool ev = g->profiling == 1 || (g->profiling == 2 && (kind == K_BATH || kind == K_CLOSURE));
         if (ev) {
             pe.a = take_event(g);
             pe.b = take_event(g);

@@ -374,9 +374,10 @@ class Grid:
         """Resume from a file written by save_state on a grid of the same set-up."""
         _check(lib().fdtdb_load_state(self.h, os.fsencode(path)))
 
-    def set_profiling(self, on, dispersive_only: bool = False):
-        """Events around every E/H launch (on), or only around dispersive-material E launches."""
-        _check(lib().fdtdb_set_profiling(self.h, 0 if not on else (2 if dispersive_only else 1)))
+    def set_profiling(self, on, bath_only: bool = False):
+        """Events around every E/H launch (on), or only around the E launches of Lorentz-Bath and
+        learned-closure materials."""
+        _check(lib().fdtdb_set_profiling(self.h, 0 if not on else (2 if bath_only else 1)))
 
     def kernel_records(self):
         n = C.c_int()
