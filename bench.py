@@ -27,6 +27,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,10 +39,12 @@ HBM_PEAK_GBS = 8000.0
 KIND = {0: "background", 1: "drude", 2: "lorentz_bath", 3: "closure"}
 
 
-def source_hash() -> str:
-    """Hash of the dominant kernel's source text (the Lorentz-Bath E kernel and the helpers it calls),
-    so that counters taken on it stay valid while other kernels change."""
-    src = open(os.path.join(ROOT, "paper_2505_23963_amd", "csrc", "fdtdb_kernels.hip")).read()
+def source_hash(src: str = None) -> str:
+    """Hash of the dominant kernel's code (the Lorentz-Bath E kernel and the helpers it calls, with
+    comments and whitespace removed), so that counters taken on it stay valid while other kernels or
+    comments change."""
+    if src is None:
+        src = open(os.path.join(ROOT, "paper_2505_23963_amd", "csrc", "fdtdb_kernels.hip")).read()
     h = hashlib.sha256()
     for start in ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
                   "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
@@ -50,7 +53,9 @@ def source_hash() -> str:
                   "void k_update_e_bath(const EArgs a"):
         s = src.find(start)
         e = src.find("\n}\n", s)
-        h.update(src[s:e].encode() if s >= 0 else start.encode())
+        body = src[s:e] if s >= 0 else start
+        code = " ".join(re.sub(r"//[^\n]*", "", body).split())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

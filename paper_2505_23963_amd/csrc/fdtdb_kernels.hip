@@ -531,8 +531,9 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
     constexpr int NC = DIM == 3 ? 3 : 1;
     // block order: with few bath streams (components x groups <= 6) blocks go in launch order, every
     // XCD streaming next to the others; with more, each XCD takes a contiguous eighth of the layer.
-    // Measured per launch: 3D N_b = 8 (3 x 2 groups) 1.69 ms in launch order against 1.73 ms; 2D
-    // N_b = 64 (1 x 16) 0.191 against 0.156 ms; 3D N_b = 16 (3 x 4) equal within noise.
+    // Measured per launch: 3D N_b = 8 (3 x 2 groups) 1.69 ms in launch order against 1.73 ms with one
+    // row per wave, 1.65 against 1.76 ms with the two-row waves below; 2D N_b = 64 (1 x 16) 0.191
+    // against 0.156 ms; 3D N_b = 16 (3 x 4) equal within noise.
     constexpr bool kLaunchOrder = NC * NG <= 6;
     const int t = (kLaunchOrder ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x;
     // 3D without energy sampling: each wave takes a 32-cell z chunk of two neighbouring y rows, so
