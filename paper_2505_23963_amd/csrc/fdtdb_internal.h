@@ -125,6 +125,11 @@ struct RegionDesc {
     // 3D H regions: psi of the z terms only for z < zlo and z >= zhi, stored per row in
     // zw = (zlo - lo[2]) + (lo[2] + ext[2] - zhi) slots; zw = 0: psi per cell of the region
     int zlo, zhi, zw;
+    // 3D E launches of Drude regions: the region's material increments V, material box and
+    // coefficients (regions of several Drude materials share one launch)
+    void *V[3];
+    int mlo[3], mext[3];
+    const double *coef;
 };
 constexpr int kMaxGroup = 32;
 // region table of a grouped launch: first blocks (unused entries hold INT_MAX, so every entry can

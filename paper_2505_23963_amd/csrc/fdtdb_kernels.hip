@@ -1100,10 +1100,10 @@ __global__ __launch_bounds__(kBlock) void k_update_h2_v4(const HArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// 3D E update of background regions (vacuum, dielectric, CPML) or of a Drude region (DRUDE:
-// the polarization increment V = P^{n+1/2} - P^{n-1/2} read and written in the same pass), four
-// z-consecutive cells per thread, regions from the launch's table (no energy sampling: launches
-// with monitors take the generic kernel).
+// 3D E update of background regions (vacuum, dielectric, CPML) or of Drude regions (DRUDE: the
+// polarization increment V = P^{n+1/2} - P^{n-1/2} read and written in the same pass, each region's
+// material from the table), four z-consecutive cells per thread, regions from the launch's table
+// (no energy sampling: launches with monitors take the generic kernel).
 // ---------------------------------------------------------------------------------------------
 template <typename T, bool DRUDE>
 __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
@@ -1144,10 +1144,10 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     // the Drude increments and the z-term psi (Ex's, Ey's) are loaded with the field rows, so that
     // their latency overlaps
     NV vv[3];
-    const int m = DRUDE ? ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]) : 0;
+    const int m = DRUDE ? ((i - D.mlo[0]) * D.mext[1] + (j - D.mlo[1])) * D.mext[2] + (k - D.mlo[2]) : 0;
     if (DRUDE) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vv[c] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(static_cast<const T *>(a.Pcur[c]) + m));
+        for (int c = 0; c < 3; ++c) vv[c] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(static_cast<const T *>(D.V[c]) + m));
     }
     V *pz0 = D.psi[0][1] ? reinterpret_cast<V *>(static_cast<T *>(D.psi[0][1]) + C.tc) : nullptr;
     V *pz1 = D.psi[1][0] ? reinterpret_cast<V *>(static_cast<T *>(D.psi[1][0]) + C.tc) : nullptr;
@@ -1183,13 +1183,13 @@ __global__ __launch_bounds__(kBlock) void k_update_e3_v4(const EArgs a) {
     double ox[4], oy[4], oz[4];
     if (DRUDE) {
         // Drude: E^{n+1/2} = E^{n-1/2} + (dt curl H - V) / eps - dt J / eps;  V' = dE E^{n+1/2} + dV V
-        const double dE = a.coef[0], dV = a.coef[1];
+        const double dE = D.coef[0], dV = D.coef[1];
         double *o3[3] = {ox, oy, oz};
         const V *ev[3] = {&ex, &ey, &ez};
         double *t1s[3] = {tx1, ty1, tz1}, *t2s[3] = {tx2, ty2, tz2};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            nvec4_t<T> *Vp = reinterpret_cast<nvec4_t<T> *>(static_cast<T *>(a.Pcur[c]) + m);
+            nvec4_t<T> *Vp = reinterpret_cast<nvec4_t<T> *>(static_cast<T *>(D.V[c]) + m);
             nvec4_t<T> vn;
             double vo[4];
 #pragma unroll

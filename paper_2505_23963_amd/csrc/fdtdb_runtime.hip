@@ -554,7 +554,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         }
         make(g->elaunch, g->regions, bg4, true, true);
         make(g->elaunch, g->regions, bg, bg.size() > 1, false);
-        make(g->elaunch, g->regions, drude4, false, true);
+        make(g->elaunch, g->regions, drude4, drude4.size() > 1, true);
         make(g->elaunch, g->regions, solo, false, false);
         std::vector<int> h4, hg;
         for (int i = 0; i < (int)g->hregions.size(); i++) {
@@ -592,6 +592,12 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
                 x.zlo = rg.zlo;
                 x.zhi = rg.zhi;
                 x.zw = rg.zw;
+                if (ph == 0 && rg.mat >= 0 && g->mats[rg.mat].kind == K_DRUDE) {
+                    const Material &mt = g->mats[rg.mat];
+                    for (int c = 0; c < 3; c++) x.V[c] = mt.P[0][c];
+                    for (int a = 0; a < 3; a++) { x.mlo[a] = (int)mt.lo[a]; x.mext[a] = mt.mext[a]; }
+                    x.coef = mt.coef_dev;
+                }
             }
             TRY(g->alloc((void **)&L.rd, sizeof(RegionTable)));
             HIP_TRY(hipMemcpy(L.rd, &tab, sizeof(RegionTable), hipMemcpyHostToDevice));
