@@ -95,7 +95,8 @@ def traffic_from_rocprof(pmc_dir: str):
 
 
 def traffic_from_profiles(kernel_tag: str, launches_cells: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches this build."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the current
+    code of the kernel."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -412,7 +413,7 @@ def main():
                          "closure2d: learned closure vs explicit bath on the 2D 2048^2 grid")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: fdtdb runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(a slab decomposition over several GPUs is designed but not built)",
               file=sys.stderr, flush=True)
         sys.exit(2)
