@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math: IEEE FP64)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11", "-fopenmp",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -60,6 +60,8 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.c_long]
         L.or_get_step.restype = C.c_long
         L.or_get_step.argtypes = [C.c_void_p]
+        L.or_set_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_get_field.argtypes = [C.c_void_p, C.c_int, _dp]
         L.or_set_field.argtypes = [C.c_void_p, C.c_int, _dp]
         L.or_get_P.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
@@ -75,6 +77,12 @@ def lib():
         L.or_destroy.argtypes = [C.c_void_p]
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads for the oracle's cell loops (OpenMP; the default is OMP_NUM_THREADS or all cores).  The
+    results do not depend on it.  n < 1 leaves it unchanged; returns the count in force."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def _ptr(a: Optional[np.ndarray]):

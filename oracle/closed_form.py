@@ -198,3 +198,30 @@ def lorentzian_bath_im_I_approx(w, omega0, Gamma, gamma_b):
 def gamma_polariton(Xc2, gamma_c, Xm2, gamma_m):
     """eq:gamma_polariton."""
     return Xc2 * gamma_c + Xm2 * gamma_m
+
+
+# ------------------------------------------------------------------ the source (Appendix, simulation details)
+def gaussian_pulse_spectrum(w, omega_c, width, amplitude=1.0):
+    """Fourier transform int J(t) exp(+i w t) dt of the soft Gaussian current
+    J(t) = A exp(-(t - t0)^2 / (2 tau^2)) cos(w_c (t - t0)), tau = 1/width, t0 = 5 tau, over all t:
+    A exp(i w t0) tau sqrt(2 pi) / 2 [exp(-tau^2 (w - w_c)^2 / 2) + exp(-tau^2 (w + w_c)^2 / 2)].
+    The source is switched off outside [0, 2 t0], where the envelope is below exp(-12.5) of its peak,
+    so a sampled run differs from this by about 1e-6 of the peak."""
+    w = np.asarray(w, dtype=np.float64)
+    tau = 1.0 / width
+    t0 = 5.0 * tau
+    g = np.exp(-tau ** 2 * (w - omega_c) ** 2 / 2.0) + np.exp(-tau ** 2 * (w + omega_c) ** 2 / 2.0)
+    return amplitude * np.exp(1j * w * t0) * tau * np.sqrt(2.0 * np.pi) / 2.0 * g
+
+
+def point_source_response_1d(w, dt, distance):
+    """E~ at `distance` nodes from a soft current J on one E node of the 1D vacuum Yee lattice, per
+    unit J~ (DFT kernel exp(+i w t), E sampled at t_{n+1/2}, J at t_n, dx = 1).
+
+    Taking the second time difference of the D line of eq:FDTD-1D and inserting the H line gives
+    E_{j+1} - 2E_j + E_{j-1} + s^2 E_j = -i s J~ delta_{j,src} with s = (2/dt) sin(w dt/2); the
+    outgoing solution is E~_j = -s J~ exp(i k |j - src|) / (2 sin k), sin(k/2) = s/2."""
+    w = np.asarray(w, dtype=np.float64)
+    k = lattice_k(w, dt)
+    s = np.sqrt(s2(w, dt))
+    return -s * np.exp(1j * k * abs(distance)) / (2.0 * np.sin(k))

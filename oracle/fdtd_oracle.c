@@ -31,6 +31,10 @@
  * is the x-y plane with (Ez, Hx, Hy).  Unused axes have extent 1 and are
  * treated as periodic, so every difference along them vanishes.
  *
+ * The cell loops of each update run in parallel over the two outer axes
+ * (OpenMP, when built with it); every cell's arithmetic is the same as in a serial loop, so the
+ * result does not depend on the thread count.  Monitor sums stay serial.
+ *
  * Boundaries per axis: periodic (wrap), closed (field values beyond the
  * grid read as zero), or CPML (closed, with a graded absorbing layer).
  * CPML is the convolutional PML of Roden and Gedney (2000) with kappa = 1,
@@ -43,6 +47,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { K_DIELECTRIC = 0, K_DRUDE = 1, K_LORENTZ = 2, K_BATH = 3, K_CLOSURE = 4 };
 enum { BC_PML = 0, BC_PERIODIC = 1, BC_CLOSED = 2 };
@@ -372,6 +379,7 @@ static void update_D(Grid *g) {
         if (!g->activeE[c]) continue;
         int a1 = CYC[c][0], a2 = CYC[c][1];
         /* (curl H)_c = d_{a1} H_{a2} - d_{a2} H_{a1} */
+#pragma omp parallel for collapse(2) schedule(static)
         for (long i = 0; i < g->n[0]; i++)
             for (long j = 0; j < g->n[1]; j++)
                 for (long k = 0; k < g->n[2]; k++) {
@@ -406,6 +414,7 @@ static void update_E(Grid *g) {
     for (int c = 0; c < 3; c++) {
         if (!g->activeE[c]) continue;
         memcpy(g->Eprev[c], g->E[c], sizeof(double) * (size_t)g->ncell);
+#pragma omp parallel for schedule(static)
         for (long q = 0; q < g->ncell; q++) {
             double P = 0.0;
             int mi = g->mat[q];
@@ -424,10 +433,11 @@ static void update_material(Grid *g, Mat *m) {
     for (int c = 0; c < 3; c++) {
         if (!g->activeE[c]) continue;
         double *Pn = m->P[c][0], *Pm = m->P[c][1];
-        long q = 0;
+#pragma omp parallel for collapse(2) schedule(static)
         for (long i = m->lo[0]; i < m->hi[0]; i++)
             for (long j = m->lo[1]; j < m->hi[1]; j++)
-                for (long k = m->lo[2]; k < m->hi[2]; k++, q++) {
+                for (long k = m->lo[2]; k < m->hi[2]; k++) {
+                    long q = ((i - m->lo[0]) * m->bn[1] + (j - m->lo[1])) * m->bn[2] + (k - m->lo[2]);
                     double E = g->E[c][IDX(g, i, j, k)];
                     double Pnew;
                     if (m->kind == K_DRUDE) {
@@ -507,6 +517,7 @@ static void update_H(Grid *g) {
         if (!g->activeH[c]) continue;
         int a1 = CYC[c][0], a2 = CYC[c][1];
         /* dH_c/dt = -(curl E)_c = -(d_{a1} E_{a2} - d_{a2} E_{a1}) */
+#pragma omp parallel for collapse(2) schedule(static)
         for (long i = 0; i < g->n[0]; i++)
             for (long j = 0; j < g->n[1]; j++)
                 for (long k = 0; k < g->n[2]; k++) {
@@ -579,10 +590,12 @@ static void accumulate_dft(Grid *g, Dft *d, int fieldE) {
     int t1, t2;
     tangents(d->axis, &t1, &t2);
     int comps[2] = {t1, t2};
-    long p = 0;
+    long bn1 = d->hi[1] - d->lo[1], bn2 = d->hi[2] - d->lo[2];
+#pragma omp parallel for collapse(2) schedule(static)
     for (long i = d->lo[0]; i < d->hi[0]; i++)
         for (long j = d->lo[1]; j < d->hi[1]; j++)
-            for (long k = d->lo[2]; k < d->hi[2]; k++, p++) {
+            for (long k = d->lo[2]; k < d->hi[2]; k++) {
+                long p = ((i - d->lo[0]) * bn1 + (j - d->lo[1])) * bn2 + (k - d->lo[2]);
                 for (int s = 0; s < 2; s++) {
                     int c = comps[s];
                     double val;
@@ -623,6 +636,17 @@ int or_step(void *gp, long nsteps) {
 }
 
 long or_get_step(void *gp) { return ((Grid *)gp)->step; }
+
+/* threads used by the cell loops (n < 1: leave unchanged); returns the count now in force */
+int or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* comp 0..2: E, 3..5: H, 6..8: D; out holds the full grid (zeros for inactive components) */
 int or_get_field(void *gp, int comp, double *out) {

@@ -159,3 +159,96 @@ def test_prepare_rebuilds_the_inputs_of_the_polarization_update(oracle_lib):
            - S[0]) / A
     assert np.max(np.abs(rhs - Pn)) < 1e-14 * np.max(np.abs(Pn))
     assert abs(np.sqrt(np.mean((Y[0] / sc[3]) ** 2)) * sc[3] - 1.0) < 1e-12
+
+
+def _exact_one_mode_closure(w, g, k, scales, eps):
+    """Weights of the tanh closure that reproduces a one-mode bath to O(eps^2): the exact linear
+    closure (hidden state Y^{m-1}, Y^{m-2}, P^{m-2}) written on the scaled inputs of the C oracle's
+    closure branch, with every pre-activation shrunk by eps and the output layer grown by 1/eps."""
+    den = 1 + 0.5 * g * DT
+    a, b, c = (2 - w ** 2 * DT ** 2) / den, -2 / den, k * DT / (2 * den)
+    sE, sP, sV, sS = scales
+    L = np.zeros((5, 7))
+    ym = np.array([0, c, 0, a, b + 1, -c, 0])
+    L[0] = ym - np.eye(7)[3]
+    L[1] = np.eye(7)[3] - np.eye(7)[4]
+    L[2] = np.array([0, 1, -DT, 0, 0, -1, 0])
+    L[4] = 0.5 * DT * k * (a * ym + b * np.eye(7)[3]) * sS
+    # the rows above act on unscaled (E, P, V, h); the network sees (E sE, P sP, V sV, h)
+    L = L / np.array([sE, sP, sV, 1, 1, 1, 1])[None, :]
+    W = 32
+    p = {"W1": np.zeros((W, 7)), "b1": np.zeros(W), "W2": np.zeros((W, W)), "b2": np.zeros(W),
+         "W3": np.zeros((5, W)), "b3": np.zeros(5)}
+    p["W1"][:7] = eps * np.eye(7)
+    p["W2"][:7, :7] = np.eye(7)
+    p["W3"][:, :7] = L / eps
+    return p, float(k * k * DT / (2 * den))
+
+
+def _cavity_1d(mat_kw, steps):
+    from fdtdb_inputs.problem import CLOSED, Source
+    p = Problem(name="cl1d", ndim=1, n=(120, 1, 1), bc=(CLOSED, PERIODIC, PERIODIC), dtype="f64", steps=steps)
+    p.materials.append(LorentzBath(box((30, 100)), omega0=1.0, gamma0=0.01, eps_inf=1.0, sigma=0.1, **mat_kw))
+    p.sources.append(Source(comp=2, box=box((20, 21)), omega_c=1.0, width=0.5, amplitude=0.3))
+    return p
+
+
+def test_c_closure_branch_carries_the_exact_one_mode_closure(oracle_lib):
+    """The C oracle's learned-closure branch, given the exact linear closure of a one-mode bath carried
+    into tanh by eps-scaling, advances a 1D cavity exactly as the explicit N_b = 1 bath does (to the
+    O(eps^2) of tanh's cubic term), on inputs scaled by four different factors.  The bath is strong
+    enough that leaving it out, or feeding the closure a velocity off by the 1/dt factor, moves E by
+    more than 1e-3."""
+    w, g, k = np.array([1.05]), np.array([0.03]), np.array([0.3])
+    steps = 1500
+    pe = _cavity_1d(dict(n_bath=1, omega_j=w, gamma_j=g, k_j=k), steps)
+    oe = oracle_lib.run(pe)
+    scales = (2.0, 3.0, 5.0, 7.0)
+    wts, skc = _exact_one_mode_closure(w[0], g[0], k[0], scales, 1e-4)
+    pc = _cavity_1d(dict(n_bath=1, omega_j=w, gamma_j=g, k_j=k), steps)
+    oc = oracle_lib.run(pc, closures={0: {"weights": cl.flatten(wts), "scales": scales, "sum_kc": skc, "width": 32}})
+    ref = oe.field(2)
+    err = np.linalg.norm(oc.field(2) - ref) / np.linalg.norm(ref)
+    assert err < 1e-6, err
+    errP = np.linalg.norm(oc.polarization(0, 2, 0) - oe.polarization(0, 2, 0)) / np.linalg.norm(oe.polarization(0, 2, 0))
+    assert errP < 1e-6, errP
+    # the hidden state holds the lagged bath coordinate: h0 = Y^{n-1/2} of the explicit run
+    assert np.max(np.abs(oc.hidden(0, 2)[:, 0] - oe.bath(0, 2, 1)[0])) < 1e-6 * np.max(np.abs(oe.bath(0, 2, 1)))
+    # the bath matters at this coupling, and so does the velocity input's 1/dt
+    pl = _cavity_1d(dict(n_bath=0), steps)
+    assert np.linalg.norm(oracle_lib.run(pl).field(2) - ref) / np.linalg.norm(ref) > 1e-3
+    wrong, _ = _exact_one_mode_closure(w[0], g[0], k[0], (2.0, 3.0, 5.0 * DT, 7.0), 1e-4)
+    ow = oracle_lib.run(_cavity_1d(dict(n_bath=1, omega_j=w, gamma_j=g, k_j=k), steps),
+                        closures={0: {"weights": cl.flatten(wrong), "scales": scales, "sum_kc": skc, "width": 32}})
+    assert np.linalg.norm(ow.field(2) - ref) / np.linalg.norm(ref) > 1e-3
+
+
+def test_c_closure_branch_matches_the_python_forward_pass(oracle_lib):
+    """One cell of the C oracle's closure branch driven by a prescribed E, with random weights in
+    tanh's nonlinear range: the polarization it produces closes eq:Pz_update-LB with the bath force
+    o[4]/s_S of oracle/closure.forward run on the same inputs (E s_E, P^{n+1/2} s_P,
+    (P^{n+1/2} - P^{n-1/2})/dt s_V), and the final hidden states agree."""
+    rng = np.random.default_rng(21)
+    prm = {kk: rng.normal(0, 0.4, s) for kk, s in cl.shapes(32).items()}
+    prm["W3"][:4] *= 0.05
+    w0, g0, sig, skc = 1.0, 0.01, 0.08, 0.004
+    scales = np.array([1.5, 4.0, 6.0, 20.0])
+    p = Problem(name="0d", ndim=1, n=(1, 1, 1), bc=(PERIODIC, PERIODIC, PERIODIC), dtype="f64")
+    p.materials.append(LorentzBath(box((0, 1)), omega0=w0, gamma0=g0, eps_inf=1.0, sigma=sig))
+    o = oracle_lib.Oracle(p, closures={0: {"weights": cl.flatten(prm), "scales": scales, "sum_kc": skc,
+                                           "width": 32}})
+    n = np.arange(300)
+    E = np.exp(-((n - 40) / 10.0) ** 2) * np.cos(1.0 * n * DT)
+    Pn = o.drive(0, 2, E)                                  # P^{m+1} after E^m
+    P = np.concatenate([[0.0], Pn])                        # P^0 ... P^T
+    Pprev = np.concatenate([[0.0], P[:-2]])                # P^{m-1}
+    V = (P[:-1] - Pprev) / DT
+    X = np.stack([E * scales[0], P[:-1] * scales[1], V * scales[2]], axis=1)[None]
+    out, h, _ = cl.forward(prm, X, np.zeros((1, 4)))
+    S = out[0, :, 4] / scales[3]
+    A = 1 + 0.5 * g0 * DT + 0.5 * DT * skc
+    rhs = (w0 ** 2 * DT ** 2 * sig * E - (w0 ** 2 * DT ** 2 - 2) * P[:-1] - (1 - 0.5 * g0 * DT - 0.5 * DT * skc) * Pprev
+           - S) / A
+    assert np.max(np.abs(rhs - Pn)) < 1e-12 * np.max(np.abs(Pn))
+    assert np.max(np.abs(S)) > 0.1 * np.max(np.abs(Pn))
+    assert np.max(np.abs(o.hidden(0, 2)[0] - h[0, -1])) < 1e-12 * max(1.0, np.max(np.abs(h)))

@@ -353,6 +353,39 @@ def test_P6_vacuum_energy_closed_box(oracle_lib):
     assert np.max(np.abs(e[25:] - e[25])) / e[25] < 1e-12
 
 
+def test_G6_source_waveform_and_lattice_green_function(oracle_lib):
+    """The soft Gaussian current (Appendix, simulation details; tau = 1/width, t0 = 5 tau, off after
+    2 t0) radiating in 1D vacuum: the DFT of E at nodes on both sides of the source equals the lattice
+    Green's function of eq:FDTD-1D times the pulse spectrum.  Against the closed-form Fourier
+    transform of the pulse (carrier, centre time, width, amplitude and the sign of the current in the
+    D update) to the pulse's own truncation level, and against the sampled pulse J(n dt) cut off after
+    2 t0 to 5e-8 of the peak (the cut-off itself changes the spectrum by 3e-7 of the peak)."""
+    from oracle.closed_form import gaussian_pulse_spectrum, point_source_response_1d
+    w = np.linspace(0.6, 1.5, 46)
+    N, s, amp, wc, width = 3000, 1500, 0.7, 1.0, 0.2
+    # closed walls 1500 cells away: no reflection reaches the probes within 5000 steps
+    p = Problem(name="green", ndim=1, n=(N, 1, 1), bc=(CLOSED, PERIODIC, PERIODIC), dtype="f64", steps=5000)
+    p.sources.append(Source(comp=2, box=box((s, s + 1)), omega_c=wc, width=width, amplitude=amp))
+    probes = (40, 100, -60)
+    for d in probes:
+        p.dfts.append(DftFlux(0, box((s + d, s + d + 1)), w))
+    o = oracle_lib.run(p)
+    tau = 1.0 / width
+    t = np.arange(int(4 * 5 * tau / DT)) * DT
+    sampled = amp * np.exp(-(t - 5 * tau) ** 2 / (2 * tau ** 2)) * np.cos(wc * (t - 5 * tau))
+    cut = np.where(t <= 10 * tau, sampled, 0.0)
+    J_cut = (cut[None, :] * np.exp(1j * w[:, None] * t[None, :])).sum(1) * DT
+    J_all = (sampled[None, :] * np.exp(1j * w[:, None] * t[None, :])).sum(1) * DT
+    J_ft = gaussian_pulse_spectrum(w, wc, width, amp)
+    for i, d in enumerate(probes):
+        E = o.flux(i, raw=True)[1][1, 0]         # E_z accumulator of the probe node
+        G = point_source_response_1d(w, DT, d)
+        peak = np.max(np.abs(G * J_ft))
+        assert np.max(np.abs(E - G * J_ft)) < 2e-6 * peak, d
+        assert np.max(np.abs(E - G * J_cut)) < 5e-8 * peak, d
+        assert np.max(np.abs(E - G * J_all)) > 1e-7 * peak, d      # the cut-off is resolved
+
+
 # ----------------------------------------------------------------------------------------------
 def _transmission(oracle_lib, mats, w, N=800, steps=30000, width=0.2, omega_c=1.0):
     def run(ms):
@@ -573,3 +606,23 @@ def test_P9_other_axis_equals_1d(oracle_lib, ndim, axis):
     assert sc > 1e-3
     assert np.max(np.abs(e - e1)) <= 1e-13 * sc
     assert np.max(np.abs(h + h1)) <= 1e-13 * sc
+
+
+def test_oracle_threads_do_not_change_results(oracle_lib):
+    """The oracle's cell loops run in parallel; every cell's arithmetic is the serial one, so one
+    thread and several give bit-identical fields, polarization, bath, spectra and energy."""
+    from fdtdb_inputs import configs
+    p = configs.config2_3d(nx=6, ny=5, steps=60, nfreq=8, dtype="f64")
+    p.energies.append(EnergyMonitor(box((0, 6), (0, 5), (40, 470)), every=7))
+    before = oracle_lib.set_threads()
+    try:
+        outs = []
+        for n in (1, 4):
+            oracle_lib.set_threads(n)
+            o = oracle_lib.run(p)
+            outs.append([o.field(c) for c in range(6)] + [o.polarization(1, 0, 0), o.bath(1, 2, 1), o.flux(0),
+                                                          o.energy(0)])
+    finally:
+        oracle_lib.set_threads(before)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
