@@ -1,24 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the FDTD-Bath time step on one MI355X.
 
-Workload: the 3D planar cavity, 256 x 256 x 512 cells, periodic in x and y,
-CPML in z, Drude mirrors around a 400-cell Lorentz-Bath layer with
-N_b = 8 bath modes per cell and E component (per-cell sigma), a plane
-Gaussian source and a 256-frequency FP64 z-flux DFT plane.  FP32 state, FP64
-register arithmetic and FP64 DFT accumulators.
+Default workload: the large 3D grid, 512 x 512 x 512 cells (134 M), periodic in x and y, CPML in z,
+a 205-cell Lorentz-Bath slab (40 % of z) with N_b = 16 explicit bath modes per cell and E component,
+a Gaussian-profile plane source and a 256-frequency FP64 z-flux DFT plane; FP32 state, FP64 register
+arithmetic, FP64 DFT accumulators.
 
-One step = the whole time step: clock/source, every region's E and material
-update (Lorentz-Bath bath force, polarization and bath modes), every region's
-H update (CPML included), DFT staging, and the blocked DFT flush (every 64
-steps; the default 64 timed steps include one flush, so its cost is spread
-over the steps as in a long run).
+One step = the whole time step: clock/source, every region's E and material update (bath force,
+polarization and bath modes), every region's H update (CPML included), DFT staging and the blocked
+DFT flush.  The flush runs once per 64 steps, so the warm-up and the timed region are both whole
+64-step periods (a request for K steps times 64 * ceil(K / 64)), and every timed step carries its
+share of the flush.
 
-Prints one JSON line.  `value` is cell-updates per second (Gcell-updates/s)
-over the timed steps with all state resident in HBM.  `roofline` is the
-dominant kernel's algorithmic HBM bytes per launch over its average launch
-time, from HIP events recorded around each launch on the library's stream.
-`cpu_baseline` times the FP64 CPU oracle on a cropped sample of the same
-workload.
+Prints one JSON line.  `value` is cell-updates per second (Gcell-updates/s) over the timed steps with
+all state resident in HBM.  `roofline` is the dominant kernel's algorithmic HBM bytes per launch over
+its average launch time, from HIP events recorded around each launch on the library's stream;
+`step_roofline` is the whole step's algorithmic bytes over the step time.  `cpu_baseline` times the
+FP64 CPU oracle on crops of the same layout (one thread, and every thread the host gives it) and
+states the GPU's error against it on that crop (`parity`).  `learned` compares the K = 4 learned
+closure in place of the explicit bath.
 """
 from __future__ import annotations
 
@@ -39,18 +39,30 @@ HBM_PEAK_GBS = 8000.0
 KIND = {0: "background", 1: "drude", 2: "lorentz_bath", 3: "closure"}
 
 
-def source_hash(src: str = None) -> str:
-    """Hash of the dominant kernel's code (the Lorentz-Bath E kernel and the helpers it calls, with
-    comments and whitespace removed), so that counters taken on it stay valid while other kernels or
-    comments change."""
+# the functions each counted kernel consists of (its own code and the helpers it calls)
+KERNEL_CODE = {
+    "E_lorentz_bath_nb8": ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
+                           "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
+                           "__device__ __forceinline__ void unflatten(", "__device__ __forceinline__ double z_minus_lane(",
+                           "__device__ __forceinline__ double minus_lane_pairs(",
+                           "__host__ __device__ inline long long pair_threads(", "void k_update_e_bath(const EArgs a"),
+    "E_lorentz_bath_nb16": ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
+                            "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
+                            "__device__ __forceinline__ void unflatten(", "__device__ __forceinline__ void bath_component(",
+                            "void k_update_e_bath_c(const EArgs a"),
+}
+# rocprofv3 kernel-name patterns of the counted kernels
+KERNEL_NAMES = {"k_update_e_bath<3, float, 2,": "E_lorentz_bath_nb8", "k_update_e_bath_c<float, 4>": "E_lorentz_bath_nb16"}
+
+
+def source_hash(tag: str = "E_lorentz_bath_nb16", src: str = None) -> str:
+    """Hash of a counted kernel's code (its function and the helpers it calls, with comments and
+    whitespace removed), so that counters taken on it stay valid while other kernels or comments
+    change."""
     if src is None:
         src = open(os.path.join(ROOT, "paper_2505_23963_amd", "csrc", "fdtdb_kernels.hip")).read()
     h = hashlib.sha256()
-    for start in ("__device__ __forceinline__ double ldd(", "__device__ __forceinline__ double at_minus(",
-                  "__device__ __forceinline__ double source_term(", "__device__ __forceinline__ int xcd_block(",
-                  "__device__ __forceinline__ void unflatten(", "__device__ __forceinline__ double z_minus_lane(",
-                  "__device__ __forceinline__ double minus_lane_pairs(", "__host__ __device__ inline long long pair_threads(",
-                  "void k_update_e_bath(const EArgs a"):
+    for start in KERNEL_CODE[tag]:
         s = src.find(start)
         e = src.find("\n}\n", s)
         body = src[s:e] if s >= 0 else start
@@ -61,7 +73,7 @@ def source_hash(src: str = None) -> str:
 
 def traffic_from_rocprof(pmc_dir: str):
     """Write profiles/traffic_counters.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv runs of
-    this benchmark (pmc_FETCH_SIZE/, pmc_WRITE_SIZE/) and of the copy calibration
+    this benchmark (pmc_<workload>_FETCH_SIZE/, pmc_<workload>_WRITE_SIZE/) and of the copy calibration
     (pmccopy_FETCH_SIZE/, pmccopy_WRITE_SIZE/) under pmc_dir.  Counter KiB per dispatch are scaled
     by what the same counter reads for a device copy of known size."""
     import csv
@@ -72,64 +84,102 @@ def traffic_from_rocprof(pmc_dir: str):
             d.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
         return {k: sum(v) / len(v) for k, v in d.items()}
 
-    out = {"source_hash": source_hash(), "kernels": {}, "calibration": {}}
+    out = {"kernels": {}, "calibration": {}}
     cal = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         cp = per_kernel(os.path.join(pmc_dir, f"pmccopy_{c}", "run_counter_collection.csv"))
         kib = max(v for k, v in cp.items() if "copyBuffer" in k)
         cal[c] = (1 << 30) / (kib * 1024.0)          # the calibration copies 1 GiB
         out["calibration"][c] = {"copy_bytes": 1 << 30, "counter_kib": kib, "scale": cal[c]}
-    f = per_kernel(os.path.join(pmc_dir, "pmc_FETCH_SIZE", "run_counter_collection.csv"))
-    w = per_kernel(os.path.join(pmc_dir, "pmc_WRITE_SIZE", "run_counter_collection.csv"))
-    tags = {"k_update_e_bath<3, float, 2,": "E_lorentz_bath_nb8"}
-    for name, kib in f.items():
-        for pat, tag in tags.items():
-            if pat in name and name in w:
-                rd = kib * 1024.0 * cal["FETCH_SIZE"]
-                wr = w[name] * 1024.0 * cal["WRITE_SIZE"]
-                out["kernels"][tag] = {"kernel": name, "fetch_kib": kib, "write_kib": w[name], "read_bytes": rd,
-                                       "write_bytes": wr, "hbm_bytes_per_launch": rd + wr}
+    for wl in sorted(glob.glob(os.path.join(pmc_dir, "pmc_*_FETCH_SIZE"))):
+        f = per_kernel(os.path.join(wl, "run_counter_collection.csv"))
+        w = per_kernel(os.path.join(wl.replace("FETCH_SIZE", "WRITE_SIZE"), "run_counter_collection.csv"))
+        for name, kib in f.items():
+            for pat, tag in KERNEL_NAMES.items():
+                if pat in name and name in w:
+                    rd = kib * 1024.0 * cal["FETCH_SIZE"]
+                    wr = w[name] * 1024.0 * cal["WRITE_SIZE"]
+                    out["kernels"][tag] = {"kernel": name, "source_hash": source_hash(tag), "fetch_kib": kib,
+                                           "write_kib": w[name], "read_bytes": rd, "write_bytes": wr,
+                                           "hbm_bytes_per_launch": rd + wr}
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out, indent=1))
 
 
-def traffic_from_profiles(kernel_tag: str, launches_cells: int):
+def traffic_from_profiles(kernel_tag: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the current
     code of the kernel."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path))
+        k = json.load(open(path)).get("kernels", {}).get(kernel_tag)
     except ValueError:
         return None
-    if d.get("source_hash") != source_hash():
-        return None
-    k = d.get("kernels", {}).get(kernel_tag)
-    if not k:
+    if not k or k.get("source_hash") != source_hash(kernel_tag):
         return None
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The oracle as it stands, single thread, on a 16 x 16 x 512 crop of the workload."""
+def _oracle_rate(p, threads: int, seconds_target: float):
+    """Cell-updates/s of the oracle as it stands on problem p with the given thread count: whole runs of
+    5 steps from rest until about seconds_target have passed.  Returns (rate, steps, seconds, threads,
+    oracle)."""
     import oracle
-    from fdtdb_inputs import configs
     oracle.build(force=False)
-    p = configs.config2_3d(nx=16, ny=16, steps=0, nfreq=256)
+    used = oracle.set_threads(threads)
     o = oracle.Oracle(p)
-    o.step(2)
     t0 = time.perf_counter()
     steps = 0
     while time.perf_counter() - t0 < seconds_target:
         o.step(5)
         steps += 5
     dt = time.perf_counter() - t0
-    cells = p.cells
-    return {"value": cells * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, one thread, 16x16x512 crop of the same layout (N_b=8, 256-frequency DFT), "
-                      f"{steps} steps in {dt:.1f} s"}
+    return p.cells * steps / dt, steps, dt, used, o
+
+
+def _crop_parity(p, o, steps, stream):
+    """The GPU's errors against the oracle o after the same `steps` on crop p: relative L2 of E, H, and
+    the bath layer's P and Y (all components)."""
+    import numpy as np
+    from paper_2505_23963_amd import Grid
+    g = Grid(p, stream=stream)
+    g.step(steps)
+    g.synchronize()
+    out = {}
+    groups = {"E": [(lambda x, c=c: x.field(c)) for c in range(3)],
+              "H": [(lambda x, c=c: x.field(c)) for c in range(3, 6)]}
+    mi = next(i for i, m in enumerate(p.materials) if type(m).__name__ == "LorentzBath")
+    groups["P"] = [(lambda x, c=c: x.polarization(mi, c, 0)) for c in range(3)]
+    groups["Y"] = [(lambda x, c=c: x.bath(mi, c, 0)) for c in range(3)]
+    for k, gets in groups.items():
+        d = sum(float(np.linalg.norm(f(g) - f(o))) ** 2 for f in gets)
+        n = sum(float(np.linalg.norm(f(o))) ** 2 for f in gets)
+        out[k] = float("%.3e" % (np.sqrt(d / n) if n > 0 else 0.0))
+    return out
+
+
+def cpu_baseline(make_crop, crop_one: str, crop_all: str, seconds_target: float = 12.0, stream=None):
+    """The FP64 oracle as it stands, timed on crops of the workload: one thread on the smaller crop and every
+    thread the host gives it (OMP_NUM_THREADS, else all cores) on the larger one; then the GPU on the small
+    crop for the same steps, and its error against the oracle there."""
+    import os as _os
+    n_all = int(_os.environ.get("OMP_NUM_THREADS", "0") or 0) or (_os.cpu_count() or 1)
+    p1 = make_crop(crop_one)
+    r1, st1, dt1, _, o1 = _oracle_rate(p1, 1, seconds_target)
+    pa = make_crop(crop_all)
+    ra, sta, dta, used, oa = _oracle_rate(pa, n_all, seconds_target)
+    del oa
+    parity = _crop_parity(p1, o1, st1, stream)
+    return {"value": round(ra / 1e9, 6), "unit": "Gcell-updates/s", "cores": used, "kind": "oracle",
+            "sample": f"FP64 oracle, {used} threads, {crop_all} crop of the same layout, {sta} steps from rest in "
+                      f"{dta:.1f} s",
+            "one_core": {"value": round(r1 / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
+                         "sample": f"{crop_one} crop, {st1} steps from rest in {dt1:.1f} s"},
+            "parity": {"crop": crop_one, "steps": st1, "rel_l2": parity,
+                       "measure": "relative L2 over all components of each field after the same steps, GPU FP32 "
+                                  "state against the FP64 oracle"}}
 
 
 def copy_calibration(gib: float = 1.0, reps: int = 5):
@@ -177,7 +227,7 @@ def bench_cavities(args):
     print(json.dumps({
         "metric": METRIC, "value": round(cells * steps / dt / 1e9, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(dt / steps * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "64 batched 1D cavities, L ~ U[1500,4000], N_b=32, FP32 state, per-cavity 512-frequency "
                                "DFT and bath energy every 10 steps", "cells": cells, "tiling": list(b.tiling)},
         "hbm_equivalent_GBps": round(per_step / (dt / steps) / 1e9, 1),
@@ -320,19 +370,97 @@ def bench_closure2d(args):
     }), flush=True)
 
 
+def _whole_periods(n: int) -> int:
+    """Steps rounded up to whole 64-step DFT flush periods (at least one)."""
+    return 64 * max(1, -(-int(n) // 64))
+
+
+def timed_grid(p, stream, warmup: int, steps: int, closures=None, reps: int = 1):
+    """Build a grid, run `warmup` steps, then time `steps` steps (bracketed by device synchronisation)
+    with HIP events around the Lorentz-Bath or closure launches.  Returns the seconds of the first timed
+    region, of every repeat, the launch records of the first, and the grid's byte model."""
+    import torch
+    from paper_2505_23963_amd import Grid
+    g = Grid(p, stream=stream.cuda_stream, closures=closures)
+    stats = g.stats()
+    g.step(warmup)
+    g.synchronize()
+    g.set_profiling(True, bath_only=True)
+    g.kernel_records()                        # start from empty event lists
+    times, recs = [], None
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if r == 0:
+            recs = g.kernel_records()
+    g.synchronize()                           # watchdog (outside the timed region)
+    del g
+    return times, recs, stats
+
+
 def bench_large3d(args):
-    """The 512^3 grid (Lorentz-Bath slab over 40 % of z, N_b = 16 Ohmic): explicit bath vs learned closure,
-    cell-updates/s of both and the closure's errors against the explicit run on a 64 x 64 x 512 crop."""
+    """The 512^3 grid (Lorentz-Bath slab over 40 % of z, N_b = 16 Ohmic, explicit bath): the benchmark line.
+    Extras: the median of five more timed regions, the K = 4 learned closure in place of the bath
+    (trained on a 32 x 32 crop) with its errors against the explicit run on a 64 x 64 crop."""
     import numpy as np
     import torch
     from fdtdb_inputs import configs
-    from fdtdb_inputs.philox import Stream
-    from paper_2505_23963_amd import Grid, closure
     torch.cuda.init()
     stream = torch.cuda.Stream()
+    warmup, steps = _whole_periods(args.warmup), _whole_periods(args.steps)
+    p = configs.config5_3d_large(steps=0)
+    print(f"[bench] 512^3 explicit bath: warm-up {warmup}, timed {steps} steps (x6)", file=sys.stderr, flush=True)
+    times, recs, stats = timed_grid(p, stream, warmup, steps, reps=6)
+    elapsed = times[0]
+    dom = max(recs, key=lambda r: r["ms_total"])
+    avg_ms = dom["ms_total"] / max(dom["launches"], 1)
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    tag = f"E_{KIND[dom['kind']]}_nb{dom['n_bath']}"
+    ms_step = elapsed / steps * 1e3
+    step_gbps = stats["bytes_per_step"] / (ms_step * 1e-3) / 1e9
+    value = p.cells * steps / elapsed / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
+        "steps_requested": args.steps, "warmup": warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D 512x512x512 (134M cells), periodic x,y, CPML z (32 cells), 205-cell Lorentz-Bath "
+                               "slab (40% of z, sigma 0.05, N_b=16 Ohmic bath modes, explicit), Gaussian-profile "
+                               "plane source, 256-frequency FP64 z-flux plane",
+                   "cells": p.cells, "bath_cells": stats["bath_cells"], "n_bath": 16, "state_dtype": "f32",
+                   "arith_dtype": "f64", "dft_dtype": "f64", "flush_period_steps": 64, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(tag),
+                     "kernel": tag, "bytes_per_launch": dom["bytes"], "avg_launch_ms": round(avg_ms, 4),
+                     "cells_per_launch": dom["cells"]},
+        "step_roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(step_gbps / HBM_PEAK_GBS, 4), "bytes_per_step": stats["bytes_per_step"]},
+        "repeats_ms_per_step": [round(t / steps * 1e3, 4) for t in times],
+        "median_ms_per_step": round(float(np.median(times[1:])) / steps * 1e3, 4),
+    }
+    if not args.no_learned:
+        out["learned"] = _learned_large3d(args, stream, warmup, steps, value)
+    if not args.no_cpu_baseline:
+        print("[bench] oracle on crops", file=sys.stderr, flush=True)
+
+        def crop(spec):
+            nx, ny = (int(v) for v in spec.split("x")[:2])
+            return configs.config5_3d_large(nx=nx, ny=ny, steps=0)
+        out["cpu_baseline"] = cpu_baseline(crop, "16x16x512", "64x64x512", stream=stream.cuda_stream)
+    print(json.dumps(out), flush=True)
+
+
+def _learned_large3d(args, stream, warmup, steps, v_exp):
+    """The learned closure on the same grid: cell-updates/s and its errors against the explicit bath."""
+    import numpy as np
+    from fdtdb_inputs import configs
+    from fdtdb_inputs.philox import Stream
+    from paper_2505_23963_amd import Grid, closure
     s = stream.cuda_stream
-    steps = args.steps
-    # closure trained on a 32 x 32 crop of the same layout (Ex trajectories of 8192 bath cells)
+    print("[bench] learned closure: record and train on a 32 x 32 crop", file=sys.stderr, flush=True)
     rec = configs.config5_3d_large(nx=32, ny=32)
     ncell = 32 * 32 * 205
     cells = np.unique(Stream(1005, 5).integers(11000, 0, ncell - 1))[:8192]
@@ -341,29 +469,10 @@ def bench_large3d(args):
     res = closure.train(E, P, rec.courant, rec.materials[0], configs.closure_init(5), stream=s)
     t_train = time.perf_counter() - t0
     cl = {0: {"weights": res["weights"], "scales": res["scales"]}}
-    p = configs.config5_3d_large()
-
-    def timed(closures=None):
-        g = Grid(p, stream=s, closures=closures)
-        g.step(args.warmup)
-        g.synchronize()
-        g.set_profiling(True, bath_only=True)
-        g.kernel_records()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        g.step(steps)
-        g.synchronize()
-        dt = time.perf_counter() - t
-        recs = g.kernel_records()
-        lb = max((r for r in recs if r["phase"] == 0), key=lambda r: r["ms_total"])
-        out = (p.cells * steps / dt / 1e9, dt / steps * 1e3, lb["ms_total"] / max(lb["launches"], 1), lb["bytes"])
-        del g
-        return out
-
-    print("[bench] explicit 512^3", file=sys.stderr, flush=True)
-    v_exp, ms_exp, k_exp, b_exp = timed()
-    print("[bench] closure 512^3", file=sys.stderr, flush=True)
-    v_cl, ms_cl, k_cl, _ = timed(cl)
+    p = configs.config5_3d_large(steps=0)
+    times, recs, _ = timed_grid(p, stream, warmup, steps, closures=cl)
+    lb = max((r for r in recs if r["phase"] == 0), key=lambda r: r["ms_total"])
+    v_cl = p.cells * steps / times[0] / 1e9
     errs = {}
     pc = configs.config5_3d_large(nx=64, ny=64)
     for horizon in (1200, 4000):
@@ -377,40 +486,74 @@ def bench_large3d(args):
         del gc
         errs[str(horizon)] = {"spectral": float(np.max(np.abs(fc - fe)) / np.max(np.abs(fe))),
                               "field": float(np.linalg.norm(ec - ee) / np.linalg.norm(ee))}
-    print(json.dumps({
-        "metric": METRIC, "value": round(v_exp, 4), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_exp, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "3D 512x512x512, periodic x,y, CPML z, 205-cell Lorentz-Bath slab (N_b=16 Ohmic), "
-                               "Gaussian-profile plane source, 256-frequency FP64 z-flux plane", "cells": p.cells,
-                   "state_dtype": "f32"},
-        "roofline": {"bound": "hbm", "achieved": round(b_exp / (k_exp * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(b_exp / (k_exp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "kernel": "E_lorentz_bath_nb16", "avg_launch_ms": round(k_exp, 4), "bytes_per_launch": b_exp},
-        "learned": {"value": round(v_cl, 4), "ms_per_step": round(ms_cl, 4), "slab_kernel_ms": round(k_cl, 4),
-                    "learned_over_explicit": round(v_cl / v_exp, 3), "training_seconds": round(t_train, 1),
-                    "loss_linear": res["loss_linear"], "errors_vs_explicit_64x64_crop": errs},
-    }), flush=True)
+    return {"value": round(v_cl, 4), "ms_per_step": round(times[0] / steps * 1e3, 4),
+            "slab_kernel_ms": round(lb["ms_total"] / max(lb["launches"], 1), 4),
+            "learned_over_explicit": round(v_cl / v_exp, 3), "training_seconds": round(t_train, 1),
+            "loss_linear": res["loss_linear"], "errors_vs_explicit_64x64_crop": errs,
+            "accepted": False if max(e["spectral"] for e in errs.values()) > 1e-3 else True}
+
+
+def bench_planar3d(args):
+    """The 3D planar cavity (256 x 256 x 512, Drude mirrors, 400-cell Lorentz-Bath layer, N_b = 8, per-cell
+    sigma)."""
+    import numpy as np
+    import torch
+    from fdtdb_inputs import configs
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    warmup, steps = _whole_periods(args.warmup), _whole_periods(args.steps)
+    p = configs.config2_3d(nx=args.nx, ny=args.ny, steps=0)
+    print(f"[bench] planar cavity {p.n}: warm-up {warmup}, timed {steps} steps", file=sys.stderr, flush=True)
+    times, recs, stats = timed_grid(p, stream, warmup, steps)
+    dom = max(recs, key=lambda r: r["ms_total"])
+    avg_ms = dom["ms_total"] / max(dom["launches"], 1)
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    tag = f"E_{KIND[dom['kind']]}_nb{dom['n_bath']}"
+    ms_step = times[0] / steps * 1e3
+    step_gbps = stats["bytes_per_step"] / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(p.cells * steps / times[0] / 1e9, 4), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": steps, "steps_requested": args.steps, "warmup": warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D planar cavity 256x256x512 (periodic x,y; CPML z; Drude mirrors; 400-cell "
+                               "Lorentz-Bath layer, N_b=8, per-cell sigma; plane Gaussian source; 256-frequency FP64 "
+                               "z-flux DFT)", "cells": p.cells, "n_bath": 8, "state_dtype": "f32", "arith_dtype": "f64",
+                   "dft_dtype": "f64", "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(tag), "kernel": tag,
+                     "bytes_per_launch": dom["bytes"], "avg_launch_ms": round(avg_ms, 4), "cells_per_launch": dom["cells"]},
+        "step_roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(step_gbps / HBM_PEAK_GBS, 4), "bytes_per_step": stats["bytes_per_step"]},
+    }
+    if not args.no_cpu_baseline:
+        def crop(spec):
+            nx, ny = (int(v) for v in spec.split("x")[:2])
+            return configs.config2_3d(nx=nx, ny=ny, steps=0)
+        out["cpu_baseline"] = cpu_baseline(crop, "16x16x512", "64x64x512", stream=stream.cuda_stream)
+    print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64)
-    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=64,
+                    help="timed steps, rounded up to whole 64-step DFT flush periods")
+    ap.add_argument("--warmup", type=int, default=64, help="warm-up steps, rounded up like --steps")
     ap.add_argument("--train-epochs", type=int, default=600,
                     help="closure training epochs (closure2d; fewer only to profile the inference kernels)")
     ap.add_argument("--skip-accuracy", action="store_true",
                     help="closure2d: skip the accuracy runs against the explicit bath (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="large3d: leave out the learned-closure comparison")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from", default=None,
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--workload", choices=["planar3d", "cavities", "closure2d", "large3d", "fp1d"], default="planar3d",
-                    help="planar3d: the default 256x256x512 line; cavities: the 64-cavity batched 1D workload; "
-                         "closure2d: learned closure vs explicit bath on the 2D 2048^2 grid")
+    ap.add_argument("--workload", choices=["large3d", "planar3d", "cavities", "closure2d", "fp1d"], default="large3d",
+                    help="large3d: the 512^3 line (default); planar3d: the 256x256x512 planar cavity; cavities: the "
+                         "64-cavity batched 1D workload; closure2d: learned closure vs explicit bath on the 2D 2048^2 "
+                         "grid; fp1d: the 1D Fabry-Perot workload in FP64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: fdtdb runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -423,91 +566,8 @@ def main():
     if args.traffic_from:
         traffic_from_rocprof(args.traffic_from)
         return
-    if args.workload == "cavities":
-        bench_cavities(args)
-        return
-    if args.workload == "closure2d":
-        bench_closure2d(args)
-        return
-    if args.workload == "large3d":
-        bench_large3d(args)
-        return
-    if args.workload == "fp1d":
-        bench_fp1d(args)
-        return
-
-    import torch
-    from fdtdb_inputs import configs
-    from paper_2505_23963_amd import Grid
-
-    torch.cuda.init()
-    stream = torch.cuda.Stream()
-    p = configs.config2_3d(nx=args.nx, ny=args.ny, steps=0)
-    print(f"[bench] building grid {p.n} N_b=8", file=sys.stderr, flush=True)
-    g = Grid(p, stream=stream.cuda_stream)
-    stats = g.stats()
-    g.step(args.warmup)
-    torch.cuda.synchronize()
-    g.synchronize()
-    g.set_profiling(True, bath_only=True)   # events around the bath launches only
-    g.kernel_records()                       # start from empty event lists
-    base = {(r["region"], r["phase"]): (r["ms_total"], r["launches"]) for r in g.kernel_records()}
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step(args.steps)
-    torch.cuda.synchronize()
-    stream.synchronize()
-    elapsed = time.perf_counter() - t0
-    g.synchronize()                          # watchdog (outside the timed region)
-    recs = g.kernel_records()
-    for r in recs:
-        ms0, n0 = base[(r["region"], r["phase"])]
-        r["ms_total"] -= ms0
-        r["launches"] -= n0
-    dom = max(recs, key=lambda r: r["ms_total"])
-    avg_ms = dom["ms_total"] / max(dom["launches"], 1)
-    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
-    tag = f"E_{KIND[dom['kind']]}_nb{dom['n_bath']}" if dom["phase"] == 0 else "H"
-    traffic = traffic_from_profiles(tag, dom["cells"])
-    kern_ms = sum(r["ms_total"] for r in recs) / args.steps
-    ms_step = elapsed / args.steps * 1e3
-    cells = p.cells
-    value = cells * args.steps / elapsed / 1e9
-    out = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "Gcell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "3D planar cavity 256x256x512 (periodic x,y; CPML z; Drude mirrors; 400-cell "
-                        "Lorentz-Bath layer, N_b=8, per-cell sigma; plane Gaussian source; 256-frequency FP64 "
-                        "z-flux DFT)",
-            "cells": cells, "n_bath": 8, "state_dtype": "f32", "arith_dtype": "f64", "dft_dtype": "f64",
-            "global_batch": 1, "parallelism": "single-gpu",
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": tag, "bytes_per_launch": dom["bytes"], "avg_launch_ms": round(avg_ms, 4),
-            "cells_per_launch": dom["cells"],
-        },
-        "step_algorithmic_GBps": round(stats["bytes_per_step"] / (ms_step * 1e-3) / 1e9, 1),
-        "step_algorithmic_bytes": stats["bytes_per_step"],
-        "bath_kernel_ms_per_step": round(kern_ms, 4),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    {"large3d": bench_large3d, "planar3d": bench_planar3d, "cavities": bench_cavities, "closure2d": bench_closure2d,
+     "fp1d": bench_fp1d}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -467,6 +467,7 @@ struct fdtdb_batch_s {
     std::vector<int> offs;
     int ncells = 0;
     int en_cap = 0;
+    int en_slots = 0;            // segment slots per cavity that en_part was sized for
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
     std::vector<std::pair<void **, size_t>> state;   // device state arrays and their sizes (autotune scratch)
@@ -538,18 +539,25 @@ fdtdb_status ensure_energy(fdtdb_batch_s *b, long long last_step) {
         if (c.en_every) every = every ? std::min(every, c.en_every) : c.en_every;
     if (!every) return FDTDB_OK;
     const long long need = last_step / every + 2;
-    if (need <= b->en_cap && b->args.en_part) return FDTDB_OK;
+    // a new tile shape (allowed only before the first step) changes the segment slots per cavity, and
+    // with them the buffer's row layout: it is then allocated afresh, zeroed, with nothing to carry over
+    const bool reshaped = b->args.en_part && b->en_slots != b->seg_slots;
+    if (reshaped && b->steps > 0)
+        return bfail(FDTDB_E_STATE, "energy partials laid out for %d segment slots, tiling now has %d", b->en_slots,
+                     b->seg_slots);
+    if (!reshaped && need <= b->en_cap && b->args.en_part) return FDTDB_OK;
     const int cap = (int)std::max<long long>(need, 2 * (long long)b->en_cap);
     double *nw = nullptr;
     BHIP(hipStreamSynchronize(b->stream));
     BTRY(b->alloc((void **)&nw, 24 * (size_t)b->ncav * b->seg_slots * cap));
-    if (b->args.en_part) {
+    if (b->args.en_part && !reshaped) {
         for (long long r = 0; r < (long long)b->ncav * b->seg_slots; r++)
             BHIP(hipMemcpy(nw + r * cap * 3, b->args.en_part + r * b->en_cap * 3, 24 * (size_t)b->en_cap,
                            hipMemcpyDeviceToDevice));
     }
     b->args.en_part = nw;
     b->en_cap = cap;
+    b->en_slots = b->seg_slots;
     b->args.en_cap = cap;
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);

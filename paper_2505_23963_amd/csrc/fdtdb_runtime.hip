@@ -61,6 +61,13 @@ fdtdb_status fail(fdtdb_status st, const char *fmt, ...) {
         if (s_ != FDTDB_OK) return s_;  \
     } while (0)
 
+uint64_t fnv1a(const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    uint64_t h = 1469598103934665603ULL;
+    for (size_t i = 0; i < n; i++) { h ^= c[i]; h *= 1099511628211ULL; }
+    return h;
+}
+
 struct Material {
     int kind = K_BACKGROUND;
     int64_t lo[3], hi[3];
@@ -78,6 +85,8 @@ struct Material {
     float *cw_dev = nullptr;
     void *hid[3] = {};
     double cscale[4] = {1.0, 1.0, 1.0, 1.0};
+    // FNV-1a of the per-cell sigma values and of the closure weights as given (checkpoint fingerprint)
+    uint64_t sigma_hash = 0, weight_hash = 0;
 };
 
 struct Region {
@@ -927,6 +936,7 @@ uint64_t fingerprint(const fdtdb_grid_s *g) {
         f.v(m.kind); f.bytes(m.lo, sizeof m.lo); f.bytes(m.hi, sizeof m.hi); f.v(m.eps); f.v(m.omega0);
         f.v(m.gamma0); f.v(m.sigma0); f.v(m.sigma_per_cell); f.v(m.nb); f.vec(m.wj); f.vec(m.gj); f.vec(m.kj);
         f.vec(m.coef); f.v(m.cw_dev != nullptr); f.bytes(m.cscale, sizeof m.cscale);
+        f.v(m.sigma_hash); f.v(m.weight_hash);
     }
     f.v(g->srcs.size());
     for (auto &x : g->srcs) {
@@ -1177,6 +1187,7 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
     HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
     if (sigma_cells) {
         m.sigma_per_cell = true;
+        m.sigma_hash = fnv1a(sigma_cells, 8 * (size_t)mc);
         TRY(g->alloc(&m.sigma_dev, words(mc, g->f64)));
         TRY(write_state(g, m.sigma_dev, mc, sigma_cells));
     }
@@ -1202,6 +1213,7 @@ fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *
     for (int q = 0; q < kClosureParams; q++)
         if (!std::isfinite(weights[q])) return fail(FDTDB_E_INVALID, "non-finite closure weight");
     Material &m = g->mats[material_id];
+    m.weight_hash = fnv1a(weights, sizeof(float) * kClosureParams);
     // the weights, then their transposed copy (layers 1 and 3 of the inference kernel read it)
     if (!m.cw_dev) TRY(g->alloc((void **)&m.cw_dev, 2 * sizeof(float) * kClosureParams));
     std::vector<float> both(2 * (size_t)kClosureParams);

@@ -23,14 +23,20 @@ def test_more_than_one_gpu_is_refused():
 
 def test_kernel_hash_ignores_comments_but_not_code():
     src = open(KERNELS).read()
-    base = bench.source_hash(src)
+    base = bench.source_hash("E_lorentz_bath_nb8", src)
     s = src.index(HEAD)
     body = src.index("{", s) + 1
     commented = src[:body] + "\n    // a comment that changes nothing\n" + src[body:]
-    assert bench.source_hash(commented) == base
+    assert bench.source_hash("E_lorentz_bath_nb8", commented) == base
     e = src.index("cf.head[1] * Pc[ci]", s)
     changed = src[:e] + "cf.head[2] * Pc[ci]" + src[e + len("cf.head[1] * Pc[ci]"):]
-    assert bench.source_hash(changed) != base
+    assert bench.source_hash("E_lorentz_bath_nb8", changed) != base
+    # the component-split kernel of the 512^3 workload has its own hash over its own code
+    s2 = src.index("void bath_component(const EArgs &a")
+    e2 = src.index("cf.head[1] * Pc", s2)
+    changed2 = src[:e2] + "cf.head[2] * Pc" + src[e2 + len("cf.head[1] * Pc"):]
+    assert bench.source_hash("E_lorentz_bath_nb16", changed2) != bench.source_hash("E_lorentz_bath_nb16", src)
+    assert bench.source_hash("E_lorentz_bath_nb8", changed2) == base
 
 
 def test_counter_file_is_calibrated():

@@ -133,3 +133,23 @@ def test_batch_relaxation_rates_match_oracle(oracle_lib):
         Go = _fit_rate(eo, every, p.courant, 2 * t0, np.pi / dw)
         print(f"[gpu] cavity {c}: rate {Gg:.6e} (GPU) vs {Go:.6e} (oracle)", flush=True)
         assert Go > 0 and abs(Gg - Go) <= 1e-4 * Go, (c, Gg, Go)
+
+
+def test_batch_retile_after_step_zero_keeps_energy_layout():
+    """A tile shape set after a zero-step call (which already sized the energy partials for the first
+    shape) re-lays the energy buffer out for the new shape: the energy traces then equal those of a
+    batch given that shape from the start, bit for bit."""
+    from paper_2505_23963_amd import Batch
+    ps = cavities(3, 300, "f32", lengths=[1500, 2300, 3100])
+    a = Batch(ps, tiling=(32, 512))
+    a.step(0)
+    from paper_2505_23963_amd.fdtdb import lib, _bcheck
+    _bcheck(lib().fdtdb_batch_set_tiling(a.h, 16, 256))      # narrower tiles: more segments per cavity
+    a.step(300)
+    b = Batch(ps, tiling=(16, 256))
+    b.step(300)
+    a.synchronize()
+    b.synchronize()
+    for c in range(3):
+        assert np.array_equal(a.energy(c), b.energy(c)), c
+        assert np.array_equal(a.field(c, 2), b.field(c, 2)), c

@@ -107,3 +107,36 @@ def test_state_of_another_setup_is_refused(tmp_path):
     with pytest.raises(FdtdbError):
         c.load_state(path)
     assert c.steps_done == 4
+
+
+def test_state_of_other_weights_or_sigma_is_refused(tmp_path):
+    """The set-up fingerprint covers the learned closure's weights and the per-cell sigma values: a state
+    saved with one set of either is refused by a grid that has another (same shapes otherwise)."""
+    from paper_2505_23963_amd import FdtdbError, Grid
+    from paper_2505_23963_amd.fdtdb import closure_weights
+    d = configs.closure_init(3, hidden_scale=0.3, state_scale=1e-3, force_scale=0.05)
+    w1 = closure_weights(d)
+    w2 = w1.copy()
+    w2[100] += 1e-3
+    sc = (1.0, 10.0, 10.0, 100.0)
+    p = _closure1d()
+    a = Grid(p, closures={0: {"weights": w1, "scales": sc}})
+    a.step(10)
+    path = os.path.join(str(tmp_path), "closure.state")
+    a.save_state(path)
+    b = Grid(p, closures={0: {"weights": w2, "scales": sc}})
+    with pytest.raises(FdtdbError) as ei:
+        b.load_state(path)
+    assert ei.value.status == -6
+    Grid(p, closures={0: {"weights": w1, "scales": sc}}).load_state(path)      # same weights: accepted
+    q = _crop3d()
+    g = Grid(q)
+    g.step(5)
+    path3 = os.path.join(str(tmp_path), "crop.state")
+    g.save_state(path3)
+    r = _crop3d()
+    r.materials[1].sigma_cells = np.array(r.materials[1].sigma_cells)
+    r.materials[1].sigma_cells.flat[7] *= 1.01
+    with pytest.raises(FdtdbError) as ei:
+        Grid(r).load_state(path3)
+    assert ei.value.status == -6

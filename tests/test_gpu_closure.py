@@ -80,9 +80,22 @@ def test_closure_3d_per_cell_sigma_matches_oracle(oracle_lib):
 
 
 def test_closure_fp32_state(oracle_lib):
+    """FP32 state and FP32 network arithmetic against the FP64 oracle's closure on the same weights,
+    with the FP32 measure of tests/parity_util.py, every 150 steps."""
+    from paper_2505_23963_amd import Grid
+    from paper_2505_23963_amd.fdtdb import closure_weights
+    from tests.parity_util import TOL_F32, Lockstep
     p = configs.config4_2d(n=128, patch=(40, 88), nb=8, dtype="f32", src_x=36, flux_x=100)
-    g, o = _pair(oracle_lib, p, 0, 300)
-    _check(g, o, p, 0, 1e-4)
+    d = _weights(11)
+    g = Grid(p, closures={0: {"weights": closure_weights(d), "scales": SCALES}})
+    o = oracle_lib.Oracle(p, closures={0: {"weights": cl.flatten(d), "scales": SCALES, "sum_kc": _sum_kc(p, 0),
+                                           "width": 32}})
+    ls = Lockstep(g, o, p).run(600, 150)
+    ls.report()
+    e, c = ls.worst()
+    assert e < TOL_F32 and c < TOL_F32, (e, c)
+    ho, hg = o.hidden(0, 2), g.closure_state(0, 2)
+    assert np.max(np.abs(hg - ho)) <= TOL_F32 * max(np.max(np.abs(ho)), 1e-3)
 
 
 def test_closure_rejects_bad_use():

@@ -1,0 +1,151 @@
+"""FP32 parity at each workload's own length: the HIP path with FP32 state against the FP64 oracle
+over the full number of steps of the 1D Fabry-Perot (20 000), 3D planar-cavity (5000), batched
+cavities (50 000), 2D learned-closure workload with its explicit bath (10 000) and large 3D (4000)
+workloads, on crops the oracle runs in seconds to a minute (its cell loops use every host core), and the
+planar cavity at full size for 200 steps against stored oracle samples.
+
+Measure (tests/parity_util.py): every field (E, H, each Lorentz-Bath material's P and Y) and each of
+its components at every checkpoint, against the largest norm the oracle's field had so far; <= 1e-5.
+"""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from fdtdb_inputs import configs
+from tests.parity_util import TOL_F32, Lockstep, flux_errors
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _lockstep(oracle_lib, p, total, every):
+    from paper_2505_23963_amd import Grid
+    print(f"[gpu] {p.name} n={p.n} f32, {total} steps (checkpoint every {every})", flush=True)
+    g = Grid(p, dtype="f32")
+    o = oracle_lib.Oracle(p)
+    ls = Lockstep(g, o, p).run(total, every)
+    ls.report()
+    return ls, g, o
+
+
+def _assert_fields(ls):
+    e, c = ls.worst()
+    assert e < TOL_F32 and c < TOL_F32, (e, c)
+
+
+def test_fp32_config4_crop_10000_steps(oracle_lib):
+    """2D TM grid, CPML on every side, Lorentzian-form bath patch of N_b = 64: 256^2 with a 128^2 patch,
+    all 10 000 steps of the workload."""
+    p = configs.config4_2d(n=256, patch=(64, 192), steps=10000, nfreq=64, src_x=40, flux_x=216)
+    ls, g, o = _lockstep(oracle_lib, p, 10000, 2500)
+    _assert_fields(ls)
+    rel, _ = flux_errors(g.flux(0), o.flux(0), o.flux(0, raw=True)[1])
+    print(f"  flux rel-L2 {rel:.3e}", flush=True)
+    assert rel < TOL_F32
+
+
+def test_fp32_config2_crop_5000_steps(oracle_lib):
+    """3D planar cavity (per-cell sigma, N_b = 8, Drude mirrors, CPML), 16 x 16 x 512 crop, all 5000 steps."""
+    p = configs.config2_3d(nx=16, ny=16, steps=5000, nfreq=64)
+    ls, g, o = _lockstep(oracle_lib, p, 5000, 1000)
+    _assert_fields(ls)
+    rel, _ = flux_errors(g.flux(0), o.flux(0), o.flux(0, raw=True)[1])
+    print(f"  flux rel-L2 {rel:.3e}", flush=True)
+    assert rel < TOL_F32
+
+
+def test_fp32_config5_crop_4000_steps(oracle_lib):
+    """Large 3D layout (205-cell Lorentz-Bath slab, N_b = 16 on the component-split kernel, Gaussian-profile
+    plane source), 32 x 32 x 512 crop, all 4000 steps."""
+    p = configs.config5_3d_large(nx=32, ny=32, steps=4000, nfreq=32)
+    ls, g, o = _lockstep(oracle_lib, p, 4000, 1000)
+    _assert_fields(ls)
+    rel, _ = flux_errors(g.flux(0), o.flux(0), o.flux(0, raw=True)[1])
+    print(f"  flux rel-L2 {rel:.3e}", flush=True)
+    assert rel < TOL_F32
+
+
+def test_fp32_config1_20000_steps(oracle_lib):
+    """The 1D Fabry-Perot workload (N_b = 16) with FP32 state for all 20 000 steps.  The in-cavity flux
+    is measured against its cancellation scale; the monitor behind the opaque mirror reads FP32 rounding
+    noise of the in-cavity field (|t|^2 ~ 1e-78) and is bounded by the in-cavity flux."""
+    p = configs.config1_1d(steps=20000, dtype="f32")
+    ls, g, o = _lockstep(oracle_lib, p, 20000, 5000)
+    _assert_fields(ls)
+    rel, canc = flux_errors(g.flux(0), o.flux(0), o.flux(0, raw=True)[1])
+    print(f"  in-cavity flux rel-L2 {rel:.3e}, against its cancellation scale {canc:.3e}", flush=True)
+    assert canc < TOL_F32
+    assert np.max(np.abs(g.flux(1) - o.flux(1))) < TOL_F32 * np.max(np.abs(o.flux(0)))
+
+
+def test_fp32_config3_cavities_50000_steps(oracle_lib):
+    """All 64 batched cavities (N_b = 32, lengths 1500-4000) for the full 50 000 steps in the on-chip
+    batched launch; four cavities spanning the sigma range checked against the oracle: E and H, the
+    bath-energy trace behind the relaxation rates, and the flux against its cancellation scale."""
+    from paper_2505_23963_amd import Batch
+    ps = configs.config3_cavities(steps=50000, nfreq=128)
+    sig = np.array([p.materials[1].sigma for p in ps])
+    picks = [int(np.argmin(sig)), int(np.argsort(sig)[21]), int(np.argsort(sig)[42]), int(np.argmax(sig))]
+    print(f"[gpu] 64 cavities f32, 50000 steps; checked: {picks} (sigma {sig[picks]})", flush=True)
+    b = Batch(ps)
+    orcs = [oracle_lib.Oracle(ps[c]) for c in picks]
+    peak = {}
+    nthr = max(1, (os.cpu_count() or 4) // len(picks))
+
+    def adv(o, n):
+        oracle_lib.set_threads(nthr)
+        o.step(n)
+
+    with ThreadPoolExecutor(len(picks)) as ex:
+        for done in range(10000, 50001, 10000):
+            b.step(10000)
+            list(ex.map(lambda o: adv(o, 10000), orcs))
+            b.synchronize()
+            worst = 0.0
+            for c, o in zip(picks, orcs):
+                for comp in (2, 4):
+                    ref = o.field(comp)[:, 0, 0]
+                    peak[(c, comp)] = max(peak.get((c, comp), 0.0), np.linalg.norm(ref))
+                    err = np.linalg.norm(b.field(c, comp) - ref) / peak[(c, comp)]
+                    worst = max(worst, err)
+                    assert err < TOL_F32, (done, c, comp, err)
+            print(f"  step {done}: worst field error {worst:.2e}", flush=True)
+    for c, o in zip(picks, orcs):
+        eg, eo = b.energy(c)[:, 2], o.energy(0)[:, 2]
+        ebe = np.max(np.abs(eg - eo)) / np.max(np.abs(eo))
+        rel, canc = flux_errors(b.flux(c), o.flux(0), o.flux(0, raw=True)[1])
+        print(f"  cavity {c}: bath-energy trace {ebe:.2e}, flux rel-L2 {rel:.2e}, against its scale {canc:.2e}",
+              flush=True)
+        assert ebe < TOL_F32 and canc < TOL_F32, (c, ebe, canc)
+
+
+def test_fp32_config2_full_size_200_steps():
+    """The whole 256 x 256 x 512 planar cavity in the launch configuration the benchmark times, 200 steps,
+    against the FP64 oracle's values on eight sampled columns (tests/golden/make_config2_full_sample.py
+    wrote them from the oracle): E, H, P and Y of those columns against the columns' own norms."""
+    from paper_2505_23963_amd import Grid
+    ref = np.load(os.path.join(HERE, "golden", "config2_full_200.npz"))
+    steps, nfreq = int(ref["steps"]), int(ref["nfreq"])
+    p = configs.config2_3d(steps=steps, nfreq=nfreq)
+    print(f"[gpu] config2 full size f32, {steps} steps", flush=True)
+    g = Grid(p)
+    g.step(steps)
+    g.synchronize()
+    xs, ys = ref["columns"][:, 0], ref["columns"][:, 1]
+    got = np.stack([g.field(c)[xs, ys, :] for c in range(6)])
+    want = ref["fields"]
+    for name, sl in (("E", slice(0, 3)), ("H", slice(3, 6))):
+        err = np.linalg.norm(got[sl] - want[sl]) / np.linalg.norm(want[sl])
+        print(f"  {name} on the sampled columns: {err:.3e}", flush=True)
+        assert err < TOL_F32, (name, err)
+    nz = p.materials[1].box[1][2] - p.materials[1].box[0][2]
+    pol = np.stack([g.polarization(1, c, 0).reshape(256, 256, nz)[xs, ys, :] for c in range(3)])
+    bath = np.stack([g.bath(1, c, 0).reshape(p.materials[1].n_bath, 256, 256, nz)[:, xs, ys, :] for c in range(3)])
+    for name, a, b in (("P", pol, ref["polarization"]), ("Y", bath, ref["bath"])):
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"  {name} on the sampled columns: {err:.3e}", flush=True)
+        assert err < TOL_F32, (name, err)
+    full = np.array([np.linalg.norm(g.field(c)) for c in range(6)])
+    assert np.max(np.abs(full - ref["field_norms"]) / ref["field_norms"].max()) < TOL_F32
