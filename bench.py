@@ -367,7 +367,18 @@ def bench_closure2d(args):
                                   "peak": 157.3, "unit": "TFLOP/s",
                                   "frac": round(train_flops / res["train_seconds"] / 1e12 / 157.3, 4)}},
         "errors_vs_explicit": out_err,
+        "k4_linear_closure_bound": _k4_bound(),
     }), flush=True)
+
+
+def _k4_bound():
+    """The smallest spectral error a 4-state linear closure was found to reach on this workload's bath (a layer
+    as thick as the patch, steady state), as stored by tests/golden/make_closure_bound.py."""
+    path = os.path.join(ROOT, "tests", "golden", "closure_bound_k4.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    return {"best_spectral_error": d["best_spectral_error"], "layer_cells": d["layer_cells"], "starts": d["starts"]}
 
 
 def _whole_periods(n: int) -> int:

@@ -95,7 +95,11 @@ fdtdb_status fdtdb_destroy_grid(fdtdb_grid g);
  * added before the first fdtdb_step (E_STATE afterwards).  *material_id
  * (nullable) receives the material's index. */
 
-/* Non-dispersive background eps_inf > 0 (D = eps_inf E). */
+/* Non-dispersive background eps_inf > 0: the constitutive relation D = eps_inf E + P of Sec. II
+ * (the E line of eq:FDTD-1D with eps0 replaced by the background permittivity) with P = 0.
+ * box: cells of the grid, half-open; eps_inf: the relative permittivity of those cells.  E_INVALID
+ * for eps_inf <= 0, a box outside the grid or overlapping another material; E_STATE after the
+ * first step. */
 fdtdb_status fdtdb_set_eps_inf(fdtdb_grid g, const fdtdb_box *box, double eps_inf, int *material_id);
 
 /* Drude medium: P'' + gamma P' = omega_p^2 E, i.e. the Lorentz model of
@@ -147,17 +151,22 @@ fdtdb_status fdtdb_get_closure_state(fdtdb_grid g, int material_id, int componen
 
 /* ---------------------------------------------------------------------------- sources, monitors */
 
-/* Soft current source on E component `component` over `box`:
+/* Soft current source on E component `component` over `box` (the Gaussian source of the
+ * Appendix's simulation details, centred at omega_c with spectral width `width`; the current
+ * enters Ampere's law of Sec. II, i.e. the D line of eq:FDTD-1D):
  *   J(t) = amplitude exp(-(t - t0)^2 / (2 tau^2)) cos(omega_c (t - t0)),
  *   tau = 1/width, t0 = 5 tau, J = 0 for t > 2 t0,
- * subtracted in the D update: D^{n+1/2} += -dt J(t_n) profile(cell).
+ * subtracted in the D update: D^{n+1/2} += -dt J(t_n) profile(cell).  Before the first step only
+ * (E_STATE); at most 16 sources (E_INVALID).
  * profile: box-sized per-cell weights (NULL: 1).  The box must lie in one
  * eps_inf (E_INVALID otherwise).  *source_id is nullable. */
 fdtdb_status fdtdb_add_source(fdtdb_grid g, int component, const fdtdb_box *box, double omega_c, double width,
                               double amplitude, const double *profile, int *source_id);
 
-/* DFT flux plane normal to `axis`, one cell thick (plane->hi[axis] = plane->lo[axis] + 1),
- * through the E nodes at index p0 = plane->lo[axis].  Accumulated in FP64:
+/* DFT flux plane normal to `axis` (the flux spectra through a plane behind the structure from
+ * which the transmission spectra of Sec. IV are formed, Appendix simulation details), one cell
+ * thick (plane->hi[axis] = plane->lo[axis] + 1), through the E nodes at index p0 = plane->lo[axis].
+ * omega: nfreq angular frequencies (copied).  Accumulated in FP64:
  *   E~_c(p, w) = dt sum_{n} E_c^{n+1/2}(p) e^{i w (n+1/2) dt}
  *   H~_c(p, w) = dt sum_{n} (1/2)(H_c^{n+1}(p0 - 1/2) + H_c^{n+1}(p0 + 1/2)) e^{i w (n+1) dt}
  * for the two tangential components, and the flux along +axis
@@ -181,8 +190,11 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
  * mode is on (fdtdb_set_graph). */
 fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps);
 
-/* Wait for the grid's stream; runs the non-finite-field watchdog and returns
- * E_DIVERGED if it trips, E_DEVICE on an asynchronous device error. */
+/* Wait for the grid's stream and run the watchdog: E_DIVERGED when a field holds a non-finite
+ * value, or when the total of an energy monitor over every cell outside the CPML layers, sampled
+ * after every source has ended (t > 2 t0), exceeds twice its smallest value since then while above
+ * 1 % of its value when the sources ended (a passive grid's exact discrete energy cannot grow);
+ * E_DEVICE on an asynchronous device error. */
 fdtdb_status fdtdb_synchronize(fdtdb_grid g);
 
 /* Number of full steps enqueued so far. */
@@ -199,7 +211,7 @@ fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps);
  * source clock).  save_state synchronizes the stream and writes one binary file (host path,
  * overwritten; nothing of the caller's is retained).  load_state reads such a file into a grid
  * built with the same set-up (geometry, dtype, materials and their parameters, sources,
- * monitors, probes; per-cell sigma values and closure weights are not compared), after which stepping
+ * monitors, probes, per-cell sigma values and closure weights), after which stepping
  * continues exactly as the saved grid would have: a resumed run equals an uninterrupted one
  * bitwise.  Errors: E_INVALID for null arguments or a file that cannot be opened or written;
  * E_STATE for a file that is not a state file, is truncated, or was written by a grid with
@@ -217,8 +229,12 @@ fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int monitor_id, double *flux, double *
 /* out: capacity x 3 doubles [field, pol, bath]; *n_samples receives the number recorded. */
 fdtdb_status fdtdb_energy(fdtdb_grid g, int monitor_id, double *out, int64_t capacity, int64_t *n_samples);
 
-/* Copy a field component to a host array of n[0]*n[1]*n[2] doubles (converted to FP64). */
-fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, double *out);
+/* Copy a field component (0..5 = Ex, Ey, Ez, Hx, Hy, Hz; zeros for a component the grid does not
+ * carry), widened to FP64, into dst: n[0]*n[1]*n[2] doubles in C order.  dst_is_device = 0: dst
+ * is host memory; otherwise dst is device memory on the grid's device (the copy runs on the grid's
+ * stream; no host round trip).  The call synchronizes the grid's stream before and after the
+ * copy.  E_INVALID for a null dst or a bad component. */
+fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, void *dst, int dst_is_device);
 
 /* Overwrite a field component from n[0]*n[1]*n[2] host doubles (rounded to the storage type). */
 fdtdb_status fdtdb_set_field(fdtdb_grid g, int component, const double *in);

@@ -123,6 +123,9 @@ def lattice_transmission(w, dt, eps_cells, chi_cells):
     # cells L, L+1 are vacuum, carrying exp(i k j)
     e_next = np.exp(1j * k * (L + 1))
     e_cur = np.exp(1j * k * L)
+    # the field grows through an absorbing stack; both values are rescaled together (a linear
+    # recurrence) and the scale kept as a logarithm
+    logscale = np.zeros(len(w))
     for j in range(L - 1, -3, -1):
         # recurrence at node j+1 gives E_j from E_{j+1}, E_{j+2}
         node = j + 1
@@ -132,11 +135,15 @@ def lattice_transmission(w, dt, eps_cells, chi_cells):
             fac = 2.0 - S2
         e_prev = fac * e_cur - e_next
         e_next, e_cur = e_cur, e_prev
+        big = np.maximum(np.abs(e_cur), np.abs(e_next))
+        r = np.where(big > 1e100, big, 1.0)
+        e_cur, e_next = e_cur / r, e_next / r
+        logscale += np.log(r)
     # now e_cur = E_{-2}, e_next = E_{-1}; E_j = A exp(ikj) + B exp(-ikj)
     jm2, jm1 = -2, -1
     det = np.exp(1j * k * jm2) * np.exp(-1j * k * jm1) - np.exp(-1j * k * jm2) * np.exp(1j * k * jm1)
     A = (e_cur * np.exp(-1j * k * jm1) - e_next * np.exp(-1j * k * jm2)) / det
-    return 1.0 / np.abs(A) ** 2
+    return np.exp(-2.0 * (np.log(np.abs(A)) + logscale))
 
 
 # ------------------------------------------------------------------ closed-box modes and Rabi roots
@@ -225,3 +232,102 @@ def point_source_response_1d(w, dt, distance):
     k = lattice_k(w, dt)
     s = np.sqrt(s2(w, dt))
     return -s * np.exp(1j * k * abs(distance)) / (2.0 * np.sin(k))
+
+
+def lattice_transmission_uniform(w, dt, eps, chi, L: int):
+    """|t|^2 of one uniform layer of L cells (background eps, susceptibility chi(w)) on the 1D Yee
+    lattice, vacuum on both sides: the same stack as lattice_transmission with the L identical layer
+    steps of its recurrence taken at once.  The step matrix [[f, -1], [1, 0]], f = 2 - s2 (eps + chi),
+    raised to the L-th power is [[U_L, -U_{L-1}], [U_{L-1}, -U_{L-2}]] with the Chebyshev polynomials
+    U_n(cos q) = sin((n+1) q) / sin q at cos q = f / 2; every sine is taken relative to
+    exp((L+1) |Im q|) and that scale is restored in the logarithm, so thick absorbing layers do not
+    overflow."""
+    w = np.atleast_1d(np.asarray(w, dtype=np.float64))
+    k = lattice_k(w, dt)
+    S2 = s2(w, dt)
+    f = 2.0 - S2 * (eps + np.asarray(chi, dtype=np.complex128))
+    q = np.arccos(f / 2.0 + 0j)
+    big = (L + 1) * np.abs(q.imag)
+
+    def U(n):       # U_n(cos q) exp(-big)
+        a = 1j * (n + 1) * q
+        return (np.exp(a - big) - np.exp(-a - big)) / (2j * np.sin(q))
+
+    uL, uL1, uL2 = U(L), U(L - 1), U(L - 2)
+    fv = 2.0 - S2
+    # start (E_L, E_{L+1}) on the transmitted side, one vacuum step (node L), the layer, one vacuum step
+    e_cur, e_next = np.exp(1j * k * L), np.exp(1j * k * (L + 1))
+    e_cur, e_next = fv * e_cur - e_next, e_cur
+    e_cur, e_next = uL * e_cur - uL1 * e_next, uL1 * e_cur - uL2 * e_next
+    e_cur, e_next = fv * e_cur - e_next, e_cur
+    jm2, jm1 = -2, -1
+    det = np.exp(1j * k * jm2) * np.exp(-1j * k * jm1) - np.exp(-1j * k * jm2) * np.exp(1j * k * jm1)
+    A = (e_cur * np.exp(-1j * k * jm1) - e_next * np.exp(-1j * k * jm2)) / det
+    return np.exp(-2.0 * (np.log(np.abs(A)) + big))
+
+
+# ------------------------------------------------------------------ what a 4-state linear closure can reach
+def k4_closure_susceptibility(x, w, dt, omega0, gamma0, sigma):
+    """Susceptibility of a Lorentz medium whose bath force comes from a linear recurrent filter with four
+    states, driven by P and E (the learned closure with identity activations, or any such filter):
+    S = G_P(z) P + G_E(z) E with G_P, G_E sharing two complex-conjugate pole pairs p_m (|p_m| < 1) and
+    carrying short direct terms, z = exp(i w dt) (a causal response r p^n has the transform
+    r / (1 - p z)).  In the symbols of chi_discrete this reads
+        chi = w0^2 sigma (1 + C(w)) / (w0^2 - s2 - i g0 s1 + B(w)),
+        B = d0 + d1 z + d2 z^2 + sum_m [b_m / (1 - p_m z) + conj],  C = e0 + e1 z + sum_m [c_m / (1 - p_m z) + conj].
+    The direct terms cover every input the closure sees (E^n, P^n, P^{n-1}) with one to spare, so the
+    class holds every 4-state linear closure.  x: 17 reals (|p_1|, arg p_1, |p_2|, arg p_2, b_1, b_2
+    (complex, 4 reals), d0, d1, d2, c_1, c_2 (4 reals), e0, e1)."""
+    w = np.asarray(w, dtype=np.float64)
+    z = np.exp(1j * w * dt)
+    p = [x[0] * np.exp(1j * x[1]), x[2] * np.exp(1j * x[3])]
+    b = [x[4] + 1j * x[5], x[6] + 1j * x[7]]
+    c = [x[11] + 1j * x[12], x[13] + 1j * x[14]]
+    B = x[8] + x[9] * z + x[10] * z * z
+    Cc = x[15] + x[16] * z
+    for m in range(2):
+        B = B + b[m] / (1 - p[m] * z) + np.conj(b[m]) / (1 - np.conj(p[m]) * z)
+        Cc = Cc + c[m] / (1 - p[m] * z) + np.conj(c[m]) / (1 - np.conj(p[m]) * z)
+    return omega0 ** 2 * sigma * (1 + Cc) / (omega0 ** 2 - s2(w, dt) - 1j * gamma0 * s1(w, dt) + B)
+
+
+def k4_closure_best_error(w, dt, omega0, gamma0, sigma, wj, gj, kj, L, starts=6, seed=0):
+    """Smallest spectral error max_w |T_4 - T| / max_w T found for 4-state linear closures on the
+    transmission T of a uniform layer of L cells of the Lorentz-Bath medium (the bath of eq:chi_LB in
+    its discrete form, chi_discrete) against the same layer with the closure's susceptibility.  Local
+    least squares from `starts` seeded starting points: first the bath term B alone against the
+    explicit bath's (a pseudomode fit), then every parameter against T itself.  Returns (error, x)."""
+    from scipy.optimize import least_squares
+    w = np.asarray(w, dtype=np.float64)
+    T = lattice_transmission_uniform(w, dt, 1.0, chi_discrete(w, dt, omega0, gamma0, sigma, wj, gj, kj), L)
+    S2, S1 = s2(w, dt), s1(w, dt)
+    B_ex = -(S1 ** 2) * np.sum(kj ** 2 / (wj ** 2 - S2[:, None] - 1j * gj * S1[:, None]), axis=1)
+    lo = np.array([0, -np.pi, 0, -np.pi] + [-10] * 13, dtype=np.float64)
+    hi = np.array([0.99999, np.pi, 0.99999, np.pi] + [10] * 13, dtype=np.float64)
+
+    def B_of(x):
+        z = np.exp(1j * w * dt)
+        out = x[8] + x[9] * z + x[10] * z * z
+        for m in range(2):
+            pm = x[2 * m] * np.exp(1j * x[2 * m + 1])
+            bm = x[4 + 2 * m] + 1j * x[5 + 2 * m]
+            out = out + bm / (1 - pm * z) + np.conj(bm) / (1 - np.conj(pm) * z)
+        return out
+
+    def T_of(x):
+        return lattice_transmission_uniform(w, dt, 1.0, k4_closure_susceptibility(x, w, dt, omega0, gamma0, sigma), L)
+
+    rng = np.random.default_rng(seed)
+    best = (np.inf, None)
+    for _ in range(starts):
+        x0 = np.zeros(17)
+        x0[0], x0[1] = np.exp(-rng.uniform(0.005, 0.1) * dt), rng.uniform(0.9, 1.1) * omega0 * dt
+        x0[2], x0[3] = np.exp(-rng.uniform(0.05, 0.5) * dt), rng.uniform(0.8, 1.2) * omega0 * dt
+        x0[4:8] = rng.normal(0, 1e-3, 4)
+        r1 = least_squares(lambda x: np.concatenate([(B_of(x) - B_ex).real, (B_of(x) - B_ex).imag]), x0,
+                           bounds=(lo, hi), max_nfev=400)
+        r2 = least_squares(lambda x: T_of(x) - T, r1.x, bounds=(lo, hi), max_nfev=400)
+        err = float(np.max(np.abs(T_of(r2.x) - T)) / np.max(T))
+        if err < best[0]:
+            best = (err, r2.x)
+    return best

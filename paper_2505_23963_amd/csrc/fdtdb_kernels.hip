@@ -1369,6 +1369,13 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *f, long long n, i
     }
 }
 
+// a field in its storage type widened to FP64 into a device buffer (device-side read-out)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_f64(const T *f, long long n, double *out) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = (double)f[i];
+}
+
 // trajectory recorder: row n of the record = step n (steps beyond the capacity are not recorded)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_probe(const T *E, const T *P, const int *q, const int *m, int n,
@@ -1541,6 +1548,15 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
 
 hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s) {
     hipLaunchKernelGGL(k_dft_flux, dim3(nf), dim3(kBlock), 0, s, acc, npts, nf, flux);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f64(bool f64, const void *src, long long n, double *dst, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 8192);
+    if (f64)
+        hipLaunchKernelGGL(k_to_f64<double>, dim3(g), dim3(kBlock), 0, s, (const double *)src, n, dst);
+    else
+        hipLaunchKernelGGL(k_to_f64<float>, dim3(g), dim3(kBlock), 0, s, (const float *)src, n, dst);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
                             const double *stage, int npts, double2 *acc, hipStream_t s);
 hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s);
 hipError_t launch_nonfinite(bool f64, const void *f, long long n, int *flag, hipStream_t s);
+hipError_t launch_to_f64(bool f64, const void *src, long long n, double *dst, hipStream_t s);
 hipError_t launch_probe(bool f64, const void *E, const void *P, const int *q, const int *m, int n, const Clock *clk,
                         long long capacity, float *outE, float *outP, hipStream_t s);
 }  // namespace fdtdb
@@ -145,6 +146,10 @@ struct Energy {
     long long nslots = 0;
     double *out = nullptr;
     long long capacity = 0;
+    // watchdog over a monitor that spans the whole grid: samples examined so far, the first total
+    // after every source has ended, and the smallest total since
+    long long checked = 0;
+    double ref = -1.0, low = 0.0;
 };
 
 // trajectory recorder: E^{n+1/2} and the new P^{n+3/2} at chosen cells of one material, steps
@@ -1447,6 +1452,46 @@ fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps) {
     return FDTDB_OK;
 }
 
+// Energy watchdog: once every source has ended (t > 2 t0 of each), a passive grid's exact discrete
+// energy cannot grow (eq:H_full with the damping of eq:EOM_LorentzBath and the absorbing layers only
+// take energy out; what the layers hand back is their reflection, orders of magnitude below), so a
+// monitor over every cell outside the CPML layers whose total exceeds twice its smallest value since
+// then, while above 1 % of its value when the sources ended, marks an instability long before any
+// field overflows.
+fdtdb_status energy_watchdog(fdtdb_grid_s *g) {
+    double t_off = 0.0;
+    for (auto &x : g->srcs) t_off = std::max(t_off, 10.0 / x.width);
+    for (auto &e : g->ens) {
+        bool whole = true;
+        for (int a = 0; a < 3; a++) {
+            const int64_t l = g->bc[a] == FDTDB_BC_PML ? g->pml[a] : 0;
+            whole &= e.lo[a] <= l && e.hi[a] >= g->n[a] - l;
+        }
+        if (!whole) continue;
+        const long long n = g->steps == 0 ? 0 : (g->steps - 1) / e.every + 1;
+        const long long m = std::min<long long>(n, e.capacity);
+        if (m <= e.checked) continue;
+        std::vector<double> v(3 * (size_t)(m - e.checked));
+        HIP_TRY(hipMemcpy(v.data(), e.out + 3 * e.checked, 8 * v.size(), hipMemcpyDeviceToHost));
+        for (long long k = e.checked; k < m; k++) {
+            const double *x = &v[3 * (size_t)(k - e.checked)];
+            const double tot = x[0] + x[1] + x[2];
+            if ((double)(k * e.every) * g->dt <= t_off) continue;
+            if (e.ref < 0.0) {
+                e.ref = tot;
+                e.low = tot;
+                continue;
+            }
+            e.low = std::min(e.low, tot);
+            if (tot > 2.0 * e.low && tot > 1e-2 * e.ref)
+                return fail(FDTDB_E_DIVERGED, "energy of a whole-grid monitor grew from %.6g to %.6g after the sources "
+                                              "ended (sample at step %lld)", e.low, tot, k * e.every);
+        }
+        e.checked = m;
+    }
+    return FDTDB_OK;
+}
+
 fdtdb_status fdtdb_synchronize(fdtdb_grid g) {
     if (!g) return fail(FDTDB_E_INVALID, "null grid");
     HIP_TRY(hipMemsetAsync(g->flag_dev, 0, sizeof(int), g->stream));
@@ -1458,7 +1503,7 @@ fdtdb_status fdtdb_synchronize(fdtdb_grid g) {
     HIP_TRY(hipMemcpyAsync(&flag, g->flag_dev, sizeof(int), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     if (flag) return fail(FDTDB_E_DIVERGED, "non-finite field after %lld steps", (long long)g->steps);
-    return FDTDB_OK;
+    return energy_watchdog(g);
 }
 
 fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int id, double *flux, double *raw) {
@@ -1495,11 +1540,17 @@ fdtdb_status fdtdb_energy(fdtdb_grid g, int id, double *out, int64_t capacity, i
     return FDTDB_OK;
 }
 
-fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, double *out) {
-    if (!g || !out || component < 0 || component > 5) return fail(FDTDB_E_INVALID, "bad component");
+fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, void *dst, int dst_is_device) {
+    if (!g || !dst || component < 0 || component > 5) return fail(FDTDB_E_INVALID, "bad component");
     TRY(sync(g));
     const void *src = component < 3 ? g->E[component] : g->H[component - 3];
-    return read_state(g, src, g->ncell, out);
+    if (!dst_is_device) return read_state(g, src, g->ncell, static_cast<double *>(dst));
+    double *out = static_cast<double *>(dst);
+    if (!src) HIP_TRY(hipMemsetAsync(out, 0, 8 * (size_t)g->ncell, g->stream));
+    else if (g->f64) HIP_TRY(hipMemcpyAsync(out, src, 8 * (size_t)g->ncell, hipMemcpyDeviceToDevice, g->stream));
+    else HIP_TRY(launch_to_f64(false, src, g->ncell, out, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return FDTDB_OK;
 }
 
 fdtdb_status fdtdb_set_field(fdtdb_grid g, int component, const double *in) {
@@ -1613,6 +1664,11 @@ fdtdb_status fdtdb_load_state(fdtdb_grid g, const char *path) {
         HIP_TRY(hipMemcpy(bufs[i].first, host[i].data(), bufs[i].second, hipMemcpyHostToDevice));
     g->steps = steps;
     for (size_t i = 0; i < g->dfts.size(); i++) g->dfts[i].nstaged = staged[i];
+    for (auto &e : g->ens) {          // the watchdog re-reads the restored samples from the start
+        e.checked = 0;
+        e.ref = -1.0;
+        e.low = 0.0;
+    }
     return FDTDB_OK;
 }
 

@@ -76,7 +76,7 @@ SIGNATURES = [
     ("fdtdb_load_state", C.c_int, [C.c_void_p, C.c_char_p]),
     ("fdtdb_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp, _dp]),
     ("fdtdb_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
-    ("fdtdb_get_field", C.c_int, [C.c_void_p, C.c_int, _dp]),
+    ("fdtdb_get_field", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     ("fdtdb_set_field", C.c_int, [C.c_void_p, C.c_int, _dp]),
     ("fdtdb_get_polarization", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]),
     ("fdtdb_get_bath", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]),
@@ -303,8 +303,13 @@ class Grid:
 
     def field(self, comp: int) -> np.ndarray:
         out = np.zeros(self.p.cells, np.float64)
-        _check(lib().fdtdb_get_field(self.h, comp, _ptr(out)))
+        _check(lib().fdtdb_get_field(self.h, comp, out.ctypes.data_as(C.c_void_p), 0))
         return out.reshape(self.p.n)
+
+    def field_into(self, comp: int, device_ptr: int):
+        """Write a field component (FP64, C order) into device memory at device_ptr (e.g. a torch
+        float64 CUDA tensor's data_ptr() of n[0]*n[1]*n[2] elements)."""
+        _check(lib().fdtdb_get_field(self.h, comp, C.c_void_p(device_ptr), 1))
 
     def set_field(self, comp: int, values):
         v = _arr(values)

@@ -3,8 +3,8 @@
 FP32 state is compared with the FP64 oracle field by field: the vector E (its active components
 together), the vector H, and each Lorentz-Bath material's polarization P and bath coordinates Y (all
 components, the newest level).  The error of a field at a checkpoint is ||x_gpu - x_oracle||_2
-divided by the largest norm the oracle's field had at any checkpoint up to then (the field's scale over
-the run).  Each component is held to the same bar against the same scale.  Two properties of FP32
+divided by the largest norm the oracle's field had up to then, sampled every 50 steps (the field's scale
+over the run).  Each component is held to the same bar against the same scale.  Two properties of FP32
 storage make the scale over the run, and not the field at the compared step, the measure:
 
 * the storage rounds each stored word to 2^-24 of its value, so a component fed only by transverse
@@ -22,8 +22,9 @@ import numpy as np
 TOL_F32 = 1e-5
 
 
-def field_groups(p):
-    """[(name, getter(grid_or_oracle) -> list of component arrays)] of the fields compared."""
+def field_groups(p, closures=()):
+    """[(name, getter(grid_or_oracle) -> list of component arrays)] of the fields compared (materials
+    whose bath a learned closure replaces have no bath coordinates)."""
     from fdtdb_inputs.problem import active_components
     e, h = active_components(p.ndim)
     out = [("E", lambda x, e=e: [x.field(c) for c in e]), ("H", lambda x, h=h: [x.field(c) for c in h])]
@@ -31,26 +32,40 @@ def field_groups(p):
         if type(m).__name__ != "LorentzBath":
             continue
         out.append((f"P{mi}", lambda x, mi=mi, e=e: [x.polarization(mi, c, 0) for c in e]))
-        if m.n_bath:
+        if m.n_bath and mi not in closures:
             out.append((f"Y{mi}", lambda x, mi=mi, e=e: [x.bath(mi, c, 0) for c in e]))
     return out
 
 
 class Lockstep:
-    """Advance a GPU object and the oracle in equal chunks and measure every field at each checkpoint."""
+    """Advance a GPU object and the oracle together and measure every field at each checkpoint; the
+    oracle's field norms (the fields' scale) are taken every `norm_every` steps in between, so that
+    the scale sees the pulse at its peak."""
 
-    def __init__(self, gpu, orc, p, groups=None):
+    def __init__(self, gpu, orc, p, groups=None, closures=(), norm_every: int = 50):
         self.g, self.o, self.p = gpu, orc, p
-        self.groups = groups or field_groups(p)
+        self.groups = groups or field_groups(p, closures)
+        self.norm_every = norm_every
         self.peak = {}
         self.rows = []
+
+    def _track_norms(self):
+        for name, get in self.groups:
+            n = float(np.sqrt(sum(np.linalg.norm(r) ** 2 for r in get(self.o))))
+            self.peak[name] = max(self.peak.get(name, 0.0), n)
 
     def run(self, total: int, every: int):
         done = 0
         while done < total:
             n = min(every, total - done)
             self.g.step(n)
-            self.o.step(n)
+            k = 0
+            while k < n:
+                m = min(self.norm_every, n - k)
+                self.o.step(m)
+                k += m
+                if k < n:
+                    self._track_norms()
             done += n
             self.g.synchronize()
             self.rows.append((done, self.measure()))

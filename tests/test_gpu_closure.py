@@ -90,7 +90,7 @@ def test_closure_fp32_state(oracle_lib):
     g = Grid(p, closures={0: {"weights": closure_weights(d), "scales": SCALES}})
     o = oracle_lib.Oracle(p, closures={0: {"weights": cl.flatten(d), "scales": SCALES, "sum_kc": _sum_kc(p, 0),
                                            "width": 32}})
-    ls = Lockstep(g, o, p).run(600, 150)
+    ls = Lockstep(g, o, p, closures=(0,)).run(600, 150)
     ls.report()
     e, c = ls.worst()
     assert e < TOL_F32 and c < TOL_F32, (e, c)

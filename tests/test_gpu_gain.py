@@ -54,6 +54,8 @@ def test_closure_gain_over_no_bath_models():
            for k, (f, e) in {"closure": (fc, ec), "lorentz": (fl, el), "explicit2": (f2, e2)}.items()}
     for k, (s, f) in err.items():
         print(f"[gpu] {k}: spectral {s:.3e} field {f:.3e}", flush=True)
+    # 1e-3 is out of reach for any 4-state linear closure on this bath (tests/test_closure_bound.py: about
+    # 6e-2 in the steady-state spectrum of a patch-thick layer); before the revival the closure is held to 1e-2
     assert err["closure"][0] < 1e-2 and err["closure"][1] < 1e-2
     for k in ("lorentz", "explicit2"):
         assert err["closure"][0] < 0.1 * err[k][0] and err["closure"][1] < 0.1 * err[k][1], k

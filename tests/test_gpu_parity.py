@@ -468,3 +468,57 @@ def test_component_split_bitwise_equals_per_cell_kernel():
         assert np.array_equal(a.field(c), b.field(c)), c
     for c in range(3):
         assert np.array_equal(a.bath(0, c, 0), b.bath(0, c, 0)), c
+
+
+# ------------------------------------------------------------------------------------------ read-out, watchdog
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_field_readout_to_device_equals_host(dtype):
+    """fdtdb_get_field with a device destination writes the same FP64 values as the host read-out."""
+    import torch
+    from paper_2505_23963_amd import Grid
+    p = configs.config2_3d(nx=6, ny=5, steps=80, nfreq=8, dtype=dtype)
+    g = Grid(p)
+    g.step(80)
+    for c in range(6):
+        t = torch.full((p.cells,), float("nan"), dtype=torch.float64, device="cuda")
+        g.field_into(c, t.data_ptr())
+        assert np.array_equal(t.cpu().numpy().reshape(p.n), g.field(c)), c
+
+
+def _watchdog_box(every=5):
+    p = Problem(name="wd", ndim=1, n=(200, 1, 1), bc=(CLOSED, PERIODIC, PERIODIC), dtype="f32", steps=0)
+    p.materials.append(LorentzBath(box((80, 140)), omega0=1.0, gamma0=0.0, eps_inf=1.0, sigma=0.05, n_bath=4,
+                                   omega_j=np.linspace(0.9, 1.1, 4), gamma_j=np.zeros(4), k_j=np.full(4, 0.05)))
+    p.sources.append(Source(comp=2, box=box((40, 41)), omega_c=1.0, width=0.5))
+    p.energies.append(EnergyMonitor(box((0, 200)), every=every))
+    return p
+
+
+def test_watchdog_energy_growth():
+    """A lossless closed box with a whole-grid energy monitor runs clean; energy planted from the host after
+    the source has ended (a field ten times larger) is reported as growth by synchronize (E_DIVERGED)."""
+    from paper_2505_23963_amd import FdtdbError, Grid
+    from paper_2505_23963_amd.fdtdb import E_DIVERGED
+    g = Grid(_watchdog_box())
+    g.step(2000)
+    g.synchronize()                      # the source ended at step 40; energy exactly conserved since
+    g.set_field(2, 10.0 * g.field(2))
+    g.step(10)
+    with pytest.raises(FdtdbError) as ei:
+        g.synchronize()
+    assert ei.value.status == E_DIVERGED and "energy" in str(ei.value)
+
+
+def test_watchdog_quiet_on_absorbing_and_lossy_grids():
+    """A monitor over every cell inside the CPML layers, on a grid whose energy leaves through those
+    layers and decays in the bath, never trips the watchdog (2D grid with CPML on every side and a
+    Lorentzian-form N_b = 64 patch, FP32)."""
+    from paper_2505_23963_amd import Grid
+    p = configs.config4_2d(n=160, patch=(60, 110), steps=0, nfreq=8, src_x=40, flux_x=125)
+    p.energies.append(EnergyMonitor(box((32, 128), (32, 128)), every=10))
+    g = Grid(p)
+    for _ in range(6):
+        g.step(500)
+        g.synchronize()
+    e = g.energy(0).sum(axis=1)
+    assert e[-1] < 0.2 * e.max()
