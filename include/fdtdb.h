@@ -327,6 +327,16 @@ fdtdb_status fdtdb_batch_steps_done(fdtdb_batch b, int64_t *steps);
 fdtdb_status fdtdb_batch_get_field(fdtdb_batch b, int cav, int component, double *out);
 fdtdb_status fdtdb_batch_dft_flux(fdtdb_batch b, int cav, double *flux);
 fdtdb_status fdtdb_batch_energy(fdtdb_batch b, int cav, double *out, int64_t capacity, int64_t *n_samples);
+/* fdtdb_batch_energy for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that must not call hipMalloc): the same read-out, the same arguments and results,
+ * but the per-sample sums go through a device-resident buffer of the library (one per GPU, 65536
+ * samples = 1.5 MiB, held until the process ends) instead of a buffer allocated for the call; it
+ * calls no hipMalloc or hipFree.  At most 65536 samples per call (min(n_samples, capacity) above
+ * that: E_INVALID, nothing copied).  Every call on one GPU uses that GPU's one buffer: calls that
+ * overlap in time on one GPU (several host threads, several batches) race and must be serialized
+ * by the caller.  Each call overwrites the part of the buffer it reads back, so nothing needs to
+ * be cleared between calls. */
+fdtdb_status fdtdb_batch_energy_noalloc(fdtdb_batch b, int cav, double *out, int64_t capacity, int64_t *n_samples);
 /* Last error message of the batch calls on this thread. */
 const char *fdtdb_batch_last_error(void);
 

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -400,10 +401,20 @@ static hipError_t launch(bool f64, int nt, const Args &a, int ng, int nseg, int 
 using namespace fdtdb;
 using namespace fdtdb::batch;
 
+// Device-resident read-out buffer of fdtdb_batch_energy_noalloc: kNoAllocSamples energy samples of
+// three doubles (1.5 MiB), one copy per GPU, held until the process ends.  Host code never uses this
+// name as an address: each device's copy is reached through the pointer hipGetSymbolAddress returns,
+// taken once per device when the first batch is created on it.
+constexpr int kNoAllocSamples = 65536;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[3 * kNoAllocSamples];
+
 // ============================================================================ host runtime
 namespace {
 
 thread_local std::string b_err;
+std::mutex scratch_mu;
+double *scratch_dev[kMaxDevices] = {};     // per device: the address of its `scratch`
 
 fdtdb_status bfail(fdtdb_status st, const char *fmt, ...) {
     char buf[512];
@@ -444,6 +455,7 @@ struct HostCav {
 extern "C" const char *fdtdb_batch_last_error(void) { return b_err.c_str(); }
 
 struct fdtdb_batch_s {
+    int dev = 0;                 // the device the batch was created on
     int ncav = 0;
     bool f64 = false;
     double dt = 0.5, R0 = 1e-8;
@@ -765,7 +777,19 @@ fdtdb_status fdtdb_batch_create(int ncav, const int64_t *lengths, fdtdb_dtype dt
     if (total >= (1LL << 30)) return bfail(FDTDB_E_INVALID, "too many cells");
     int dev;
     if (hipGetDevice(&dev) != hipSuccess) return bfail(FDTDB_E_DEVICE, "no HIP device");
+    if (dev < 0 || dev >= kMaxDevices) return bfail(FDTDB_E_DEVICE, "device %d beyond the supported %d", dev, kMaxDevices);
+    {   // once per device, with that device current: the address of its copy of the read-out buffer
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        if (!scratch_dev[dev]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return bfail(FDTDB_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            scratch_dev[dev] = static_cast<double *>(ptr);
+        }
+    }
     auto *b = new fdtdb_batch_s();
+    b->dev = dev;
     b->ncav = ncav;
     b->f64 = dtype == FDTDB_F64;
     b->dt = courant;
@@ -1032,6 +1056,26 @@ fdtdb_status fdtdb_batch_energy(fdtdb_batch b, int cav, double *out, int64_t cap
     if (e == hipSuccess) e = hipMemcpy(out, d, 24 * (size_t)m, hipMemcpyDeviceToHost);
     dev_free(b->mem, d);
     if (e != hipSuccess) return bfail(FDTDB_E_DEVICE, "energy read-out: %s", hipGetErrorString(e));
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_batch_energy_noalloc(fdtdb_batch b, int cav, double *out, int64_t capacity, int64_t *n_samples) {
+    if (!b || cav < 0 || cav >= b->ncav || !b->cavs[cav].en_every) return bfail(FDTDB_E_INVALID, "no energy monitor");
+    const HostCav &hc = b->cavs[cav];
+    const long long n = b->steps == 0 ? 0 : (b->steps - 1) / hc.en_every + 1;
+    if (n_samples) *n_samples = n;
+    const long long m = std::min<long long>(n, capacity);
+    if (!out || m <= 0) return FDTDB_OK;
+    if (m > kNoAllocSamples)
+        return bfail(FDTDB_E_INVALID, "fdtdb_batch_energy_noalloc reads at most %d samples per call (asked for %lld)",
+                     kNoAllocSamples, m);
+    double *buf = scratch_dev[b->dev];
+    if (!buf) return bfail(FDTDB_E_STATE, "no read-out buffer on device %d", b->dev);
+    hipLaunchKernelGGL(k_batch_energy, dim3((m + 255) / 256), dim3(256), 0, b->stream, b->args.en_part, b->seg_slots,
+                       b->en_cap, cav, (int)m, buf);
+    BHIP(hipGetLastError());
+    BHIP(hipStreamSynchronize(b->stream));
+    BHIP(hipMemcpy(out, buf, 24 * (size_t)m, hipMemcpyDeviceToHost));
     return FDTDB_OK;
 }
 

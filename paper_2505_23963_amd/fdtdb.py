@@ -100,6 +100,7 @@ SIGNATURES = [
     ("fdtdb_batch_get_field", C.c_int, [C.c_void_p, C.c_int, C.c_int, _dp]),
     ("fdtdb_batch_dft_flux", C.c_int, [C.c_void_p, C.c_int, _dp]),
     ("fdtdb_batch_energy", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
+    ("fdtdb_batch_energy_noalloc", C.c_int, [C.c_void_p, C.c_int, _dp, C.c_int64, C.POINTER(C.c_int64)]),
     ("fdtdb_batch_last_error", C.c_char_p, []),
     ("fdtdb_add_probe", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64), C.c_int64,
                                   C.POINTER(C.c_int)]),
