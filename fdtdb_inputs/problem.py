@@ -71,6 +71,18 @@ class LorentzBath:
 
 
 @dataclass
+class MultiPole:
+    """A sum of Lorentz and Drude terms on one box: kinds[p] 'lorentz' (omega[p] = omega0, gamma[p], sigma[p])
+    or 'drude' (omega[p] = omega_p, gamma[p]; sigma unused)."""
+    box: Box
+    eps_inf: float
+    kinds: Sequence[str]
+    omega: Sequence[float]
+    gamma: Sequence[float]
+    sigma: Sequence[float]
+
+
+@dataclass
 class Source:
     comp: int
     box: Box

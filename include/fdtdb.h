@@ -124,6 +124,18 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
                                     const double *omega_j, const double *gamma_j, const double *k_j,
                                     int *material_id);
 
+/* Sum of Lorentz and Drude terms on one box (Sec. II.A: realistic susceptibilities are fitted by several
+ * such terms).  Term p is kinds[p] = 0, a Lorentz oscillator (eq:EOM_Lorentz with omega0 = omega[p],
+ * gamma = gamma[p], oscillator strength sigma[p] > 0), or 1, a Drude term (omega_p = omega[p], gamma[p];
+ * sigma[p] unused); every term is driven by the same E and advanced by its own central-difference update
+ * (eq:Pz_1D_Lorentz; for a Drude term omega0^2 is dropped from the P^n coefficient), and D = eps_inf E +
+ * sum_p P_p.  Arrays of n_terms (1..8) values, copied.  E_UNSTABLE when any omega[p] dt >= 2 or when the
+ * lossless lattice bound fails: with X = 4/dt^2, X (eps_inf + sum_p chi_p(X)) >= 4 ndim, chi_p(X) =
+ * omega_p^2 sigma_p / (omega_p^2 - X) (Drude: -omega_p^2 / X); one Lorentz term gives the bound of
+ * fdtdb_set_lorentz_bath.  Same box rules and E_STATE rule as the other materials. */
+fdtdb_status fdtdb_set_multi_term(fdtdb_grid g, const fdtdb_box *box, double eps_inf, int n_terms, const int *kinds,
+                                  const double *omega, const double *gamma, const double *sigma, int *material_id);
+
 /* Host-only map of Table 1 (Sec. III): bath form 0 = uniform, 1 = lorentzian,
  * 2 = gaussian.  Frequencies evenly spaced on [omega0 - width/2, omega0 + width/2],
  * gamma_j = bath_gamma, k_b = sqrt(2 dw dephasing / pi) with dw = width/(n_bath-1)
@@ -243,6 +255,13 @@ fdtdb_status fdtdb_set_field(fdtdb_grid g, int component, const double *in);
  * or 1 (P^{n-1/2}); box-sized host doubles.  For Drude only the difference
  * level0 - level1 is stored; level 1 then returns zero and level 0 the difference. */
 fdtdb_status fdtdb_get_polarization(fdtdb_grid g, int material_id, int component, int level, double *out);
+
+/* One term of a multi-term material (fdtdb_set_multi_term), level as above; box-sized host doubles.  A
+ * Drude term stores only its increment P^{n+1/2} - P^{n-1/2} (as fdtdb_set_drude does): level 0 returns the
+ * increment, level 1 zeros.  fdtdb_get_polarization of a multi-term material returns the sum of its terms
+ * when all are Lorentz terms, else E_INVALID. */
+fdtdb_status fdtdb_get_polarization_term(fdtdb_grid g, int material_id, int component, int level, int term,
+                                         double *out);
 
 /* Bath coordinates [n_bath][box cells] at level 0 (Y^{n+1/2}) or 1 (Y^{n-1/2}). */
 fdtdb_status fdtdb_get_bath(fdtdb_grid g, int material_id, int component, int level, double *out);

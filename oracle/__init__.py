@@ -52,6 +52,10 @@ def lib():
         L.or_add_drude.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double]
         L.or_add_lorentz_bath.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double,
                                           C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_add_multipole.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_int,
+                                       np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS"), _dp, _dp, _dp]
+        L.or_get_P_pole.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_set_P_pole.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp]
         L.or_add_closure.argtypes = [C.c_void_p, _lp, _lp, C.c_double, C.c_double, C.c_double, C.c_void_p,
                                      C.c_double, C.c_double, C.c_int, _dp, _dp]
         L.or_add_source.argtypes = [C.c_void_p, C.c_int, _lp, _lp, C.c_double, C.c_double, C.c_double, C.c_void_p]
@@ -141,6 +145,11 @@ class Oracle:
                     self._keep += [wj, gj, kj]
                     rc = L.or_add_lorentz_bath(self.g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
                                                m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj))
+            elif kind == "MultiPole":
+                kinds = np.array([{"lorentz": 0, "drude": 1}[k] for k in m.kinds], np.int32)
+                rc = L.or_add_multipole(self.g, lo, hi, m.eps_inf, len(kinds), kinds,
+                                        np.ascontiguousarray(m.omega, np.float64), np.ascontiguousarray(m.gamma, np.float64),
+                                        np.ascontiguousarray(m.sigma, np.float64))
             else:
                 raise TypeError(kind)
             if rc != 0:
@@ -189,6 +198,19 @@ class Oracle:
         if lib().or_get_P(self.g, mi, comp, level, out) != 0:
             raise ValueError("no polarization")
         return out
+
+    def pole(self, mi: int, comp: int, pole: int, level: int = 0) -> np.ndarray:
+        """Polarization of one term of a multi-term material."""
+        m = self.p.materials[mi]
+        nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
+        out = np.zeros(nc, np.float64)
+        if lib().or_get_P_pole(self.g, mi, comp, level, pole, out) != 0:
+            raise ValueError("no such term")
+        return out
+
+    def set_pole(self, mi: int, comp: int, pole: int, level: int, values: np.ndarray):
+        if lib().or_set_P_pole(self.g, mi, comp, level, pole, np.ascontiguousarray(values, np.float64).ravel()) != 0:
+            raise ValueError("no such term")
 
     def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
         m = self.p.materials[mi]

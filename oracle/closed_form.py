@@ -93,6 +93,29 @@ def chi_discrete(w, dt, omega0, gamma0, sigma, wj=None, gj=None, kj=None, drude=
     return omega0 ** 2 * sigma / den
 
 
+def chi_multipole_discrete(w, dt, kinds, omega, gamma, sigma):
+    """Susceptibility of a sum of Lorentz and Drude terms advanced by their three-level recurrences: the
+    terms are independent oscillators driven by the same E, so the sum of their discrete symbols."""
+    out = 0.0
+    for k, wp, gp, sp in zip(kinds, omega, gamma, sigma):
+        out = out + (chi_discrete(w, dt, wp, gp, 1.0, drude=True) if k == "drude" else chi_discrete(w, dt, wp, gp, sp))
+    return out
+
+
+def multipole_margin(dt, ndim, eps_inf, kinds, omega, sigma):
+    """Left side of the lossless stability condition of a sum of terms (>= 0: stable).  On the lattice a
+    mode K^2 has frequencies X = s^2 solving X (eps_inf + sum_p chi_p(X)) = K^2 with chi_p = w_p^2 sigma_p /
+    (w_p^2 - X) (Drude: -w_p^2 / X); with every w_p^2 < 4/dt^2 the largest root lies on the branch above all
+    resonances, where the left side increases, so it stays below 4/dt^2 exactly when the left side at
+    X = 4/dt^2 is at least K2max = 4 ndim.  One Lorentz term gives back lossless_margin up to a positive
+    factor."""
+    X = 4.0 / dt ** 2
+    e = eps_inf
+    for k, wp, sp in zip(kinds, omega, sigma):
+        e += -wp ** 2 / X if k == "drude" else wp ** 2 * sp / (wp ** 2 - X)
+    return X * e - 4.0 * ndim
+
+
 def lattice_k(w, dt):
     """Vacuum lattice wavenumber: sin(k/2) = sin(w dt/2) / dt (dx = 1, Courant = dt)."""
     return 2.0 * np.arcsin(np.sin(np.asarray(w) * dt / 2.0) / dt)

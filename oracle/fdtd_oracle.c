@@ -51,7 +51,9 @@
 #include <omp.h>
 #endif
 
-enum { K_DIELECTRIC = 0, K_DRUDE = 1, K_LORENTZ = 2, K_BATH = 3, K_CLOSURE = 4 };
+enum { K_DIELECTRIC = 0, K_DRUDE = 1, K_LORENTZ = 2, K_BATH = 3, K_CLOSURE = 4, K_MULTI = 5 };
+enum { POLE_LORENTZ = 0, POLE_DRUDE = 1 };
+#define MAXPOLE 8
 enum { BC_PML = 0, BC_PERIODIC = 1, BC_CLOSED = 2 };
 
 #define MAXMAT 256
@@ -73,6 +75,10 @@ typedef struct {
     double scale[4];                  /* s_E, s_P, s_V, s_S */
     double sum_kc;                    /* sum_j k_j c_j kept from the explicit bath */
     double *hid[3];                   /* 4 * ncell per E comp */
+    /* sum of Lorentz / Drude terms: P = sum_p P_p, P[c][level] holds np * ncell values (pole-major) */
+    int np;
+    int pkind[MAXPOLE];
+    double pw[MAXPOLE], pg[MAXPOLE], ps[MAXPOLE];   /* omega0 (Drude: omega_p), gamma, sigma */
 } Mat;
 
 typedef struct {
@@ -284,6 +290,29 @@ int or_add_lorentz_bath(void *gp, const long *lo, const long *hi, double omega0,
     return 0;
 }
 
+/* Sum of Lorentz and Drude terms in one box (Sec. II.A: realistic susceptibilities are fitted by
+ * several such terms): kinds[p] 0 = Lorentz (omega0, gamma, sigma), 1 = Drude (omega_p, gamma); the
+ * terms are independent oscillators driven by the same E, and D = eps_inf E + sum_p P_p. */
+int or_add_multipole(void *gp, const long *lo, const long *hi, double eps_inf, int np, const int *kinds,
+                     const double *omega, const double *gamma, const double *sigma) {
+    Grid *g = (Grid *)gp;
+    if (np < 1 || np > MAXPOLE) return -1;
+    Mat *m = new_mat(g, K_MULTI, lo, hi);
+    if (!m) return -1;
+    m->eps_inf = eps_inf;
+    set_eps(g, m, eps_inf);
+    m->np = np;
+    for (int pp = 0; pp < np; pp++) {
+        m->pkind[pp] = kinds[pp];
+        m->pw[pp] = omega[pp];
+        m->pg[pp] = gamma[pp];
+        m->ps[pp] = kinds[pp] == POLE_DRUDE ? 1.0 : sigma[pp];
+    }
+    for (int c = 0; c < 3; c++)
+        if (g->activeE[c]) { m->P[c][0] = zalloc(np * m->ncell); m->P[c][1] = zalloc(np * m->ncell); }
+    return 0;
+}
+
 /* Learned bath closure: the bath force term of eq:Pz_update-LB is produced by a
  * recurrent network with 4 hidden states per component-cell.  weights holds
  * W1[width][7], b1[width], W2[width][width], b2[width], W3[5][width], b3[5]
@@ -418,7 +447,12 @@ static void update_E(Grid *g) {
         for (long q = 0; q < g->ncell; q++) {
             double P = 0.0;
             int mi = g->mat[q];
-            if (mi >= 0 && g->m[mi].P[c][0]) P = g->m[mi].P[c][0][g->moff[q]];
+            if (mi >= 0 && g->m[mi].kind == K_MULTI) {
+                const Mat *m = &g->m[mi];
+                for (int pp = 0; pp < m->np; pp++) P += m->P[c][0][pp * m->ncell + g->moff[q]];
+            } else if (mi >= 0 && g->m[mi].P[c][0]) {
+                P = g->m[mi].P[c][0][g->moff[q]];
+            }
             g->E[c][q] = (g->D[c][q] - P) / g->eps[q];
         }
     }
@@ -430,6 +464,32 @@ static double tanh_(double x) { return tanh(x); }
 static void update_material(Grid *g, Mat *m) {
     double dt = g->dt, dt2 = dt * dt;
     if (m->kind == K_DIELECTRIC) return;
+    if (m->kind == K_MULTI) {
+        /* each term follows its own central-difference update: eq:Pz_1D_Lorentz for a Lorentz term, the
+         * same with omega0^2 dropped from the P^n coefficient for a Drude term (Sec. II.A) */
+        for (int c = 0; c < 3; c++) {
+            if (!g->activeE[c]) continue;
+#pragma omp parallel for collapse(2) schedule(static)
+            for (long i = m->lo[0]; i < m->hi[0]; i++)
+                for (long j = m->lo[1]; j < m->hi[1]; j++)
+                    for (long k = m->lo[2]; k < m->hi[2]; k++) {
+                        long q = ((i - m->lo[0]) * m->bn[1] + (j - m->lo[1])) * m->bn[2] + (k - m->lo[2]);
+                        double E = g->E[c][IDX(g, i, j, k)];
+                        for (int pp = 0; pp < m->np; pp++) {
+                            double *Pn = &m->P[c][0][pp * m->ncell + q], *Pm = &m->P[c][1][pp * m->ncell + q];
+                            double w2 = m->pw[pp] * m->pw[pp], gam = m->pg[pp];
+                            double A = 1.0 + 0.5 * gam * dt, Pnew;
+                            if (m->pkind[pp] == POLE_DRUDE)
+                                Pnew = (w2 * dt2 * E + 2.0 * (*Pn) - (1.0 - 0.5 * gam * dt) * (*Pm)) / A;
+                            else
+                                Pnew = (w2 * dt2 * m->ps[pp] * E - (w2 * dt2 - 2.0) * (*Pn) - (1.0 - 0.5 * gam * dt) * (*Pm)) / A;
+                            *Pm = *Pn;
+                            *Pn = Pnew;
+                        }
+                    }
+        }
+        return;
+    }
     for (int c = 0; c < 3; c++) {
         if (!g->activeE[c]) continue;
         double *Pn = m->P[c][0], *Pm = m->P[c][1];
@@ -557,6 +617,20 @@ static void sample_energy(Grid *g, Energy *e) {
                 Mat *m = &g->m[mi];
                 if (m->kind == K_DIELECTRIC) continue;
                 long o = g->moff[q];
+                if (m->kind == K_MULTI) {
+                    for (int c = 0; c < 3; c++) {
+                        if (!g->activeE[c]) continue;
+                        for (int pp = 0; pp < m->np; pp++) {
+                            double w2 = m->pw[pp] * m->pw[pp];
+                            double rho = m->pkind[pp] == POLE_DRUDE ? 1.0 / w2 : 1.0 / (m->ps[pp] * w2);
+                            double wr = m->pkind[pp] == POLE_DRUDE ? 0.0 : w2;
+                            double p1 = m->P[c][0][pp * m->ncell + o], p0 = m->P[c][1][pp * m->ncell + o];
+                            double v = (p1 - p0) / dt;
+                            pol += 0.5 * rho * (v * v + wr * p1 * p0);
+                        }
+                    }
+                    continue;
+                }
                 double rho, w02;
                 if (m->kind == K_DRUDE) { rho = 1.0 / (m->omega0 * m->omega0); w02 = 0.0; }
                 else { w02 = m->omega0 * m->omega0; rho = 1.0 / (m->sigma[o] * w02); }
@@ -677,7 +751,27 @@ int or_set_field(void *gp, int comp, const double *in) {
 int or_get_P(void *gp, int mi, int c, int level, double *out) {
     Grid *g = (Grid *)gp;
     if (mi < 0 || mi >= g->nmat || !g->m[mi].P[c][level]) return -1;
-    memcpy(out, g->m[mi].P[c][level], sizeof(double) * (size_t)g->m[mi].ncell);
+    const Mat *m = &g->m[mi];
+    memcpy(out, m->P[c][level], sizeof(double) * (size_t)m->ncell);
+    for (int pp = 1; m->kind == K_MULTI && pp < m->np; pp++)       /* a multi-term material: the sum */
+        for (long q = 0; q < m->ncell; q++) out[q] += m->P[c][level][pp * m->ncell + q];
+    return 0;
+}
+
+/* one term of a multi-term material: its polarization at a level, box-sized */
+int or_get_P_pole(void *gp, int mi, int c, int level, int pole, double *out) {
+    Grid *g = (Grid *)gp;
+    if (mi < 0 || mi >= g->nmat || g->m[mi].kind != K_MULTI || pole < 0 || pole >= g->m[mi].np || !g->m[mi].P[c][level])
+        return -1;
+    memcpy(out, g->m[mi].P[c][level] + pole * g->m[mi].ncell, sizeof(double) * (size_t)g->m[mi].ncell);
+    return 0;
+}
+
+int or_set_P_pole(void *gp, int mi, int c, int level, int pole, const double *in) {
+    Grid *g = (Grid *)gp;
+    if (mi < 0 || mi >= g->nmat || g->m[mi].kind != K_MULTI || pole < 0 || pole >= g->m[mi].np || !g->m[mi].P[c][level])
+        return -1;
+    memcpy(g->m[mi].P[c][level] + pole * g->m[mi].ncell, in, sizeof(double) * (size_t)g->m[mi].ncell);
     return 0;
 }
 
@@ -699,7 +793,7 @@ int or_get_hidden(void *gp, int mi, int c, double *out) {
 
 int or_set_P(void *gp, int mi, int c, int level, const double *in) {
     Grid *g = (Grid *)gp;
-    if (mi < 0 || mi >= g->nmat || !g->m[mi].P[c][level]) return -1;
+    if (mi < 0 || mi >= g->nmat || !g->m[mi].P[c][level] || g->m[mi].kind == K_MULTI) return -1;
     memcpy(g->m[mi].P[c][level], in, sizeof(double) * (size_t)g->m[mi].ncell);
     return 0;
 }
@@ -723,7 +817,9 @@ int or_drive_material(void *gp, int mi, int c, const double *e_seq, long n, doub
             for (long j = m->lo[1]; j < m->hi[1]; j++)
                 for (long k = m->lo[2]; k < m->hi[2]; k++) g->E[c][IDX(g, i, j, k)] = e_seq[s];
         update_material(g, m);
-        p_out[s] = m->P[c][0] ? m->P[c][0][0] : 0.0;
+        double P = m->P[c][0] ? m->P[c][0][0] : 0.0;
+        for (int pp = 1; m->kind == K_MULTI && pp < m->np; pp++) P += m->P[c][0][pp * m->ncell];
+        p_out[s] = P;
     }
     return 0;
 }

@@ -14,7 +14,8 @@ constexpr int kDftSlots = 64;        // steps staged before a DFT flush
 constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
 
 // Update kind of a region.
-enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3 };
+enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3, K_MULTI = 4 };
+constexpr int kMaxTerms = 8;          // Lorentz / Drude terms of one multi-term material
 
 // Learned bath closure: 7 inputs -> tanh(32) -> tanh(32) -> 5 outputs.  Weight layout (row major):
 // W1[32][7], b1[32], W2[32][32], b2[32], W3[5][32], b3[5].
@@ -160,6 +161,7 @@ struct EArgs {
     const double *coef;              // FP64 coefficient table of the material
     void *hid[3];                    // learned closure hidden state [mcells] of float4
     const float *cw;                 // learned closure weights (FP32, kClosureParams)
+    int nterm;                       // multi-term material: terms, each with its levels [term][mcells] in Pcur / Pnew
     double cscale[4];                // closure input scales s_E, s_P, s_V and 1 / s_S
     // sources and clock
     const Clock *clock;

@@ -452,6 +452,36 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                     const double v = V / a.dt;
                     ep += 0.5 * a.coef[2] * v * v;
                 }
+            } else if (KIND == K_MULTI) {
+                // sum of Lorentz / Drude terms: E sees the sum of their increments.  A Lorentz term keeps its two
+                // levels (ping-pong) and advances by its three-level update, P' = cE E - cP P - cPm P_prev; a Drude
+                // term keeps its increment V = P^{n+1/2} - P^{n-1/2} (no restoring force, so P itself never enters)
+                // and advances by V' = cE E + cV V, written to the other buffer (coefficients per term in the table)
+                T *Pc_ = static_cast<T *>(a.Pcur[c]);
+                T *Pn_ = static_cast<T *>(a.Pnew[c]);
+                double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+#pragma unroll
+                for (int p = 0; p < kMaxTerms; ++p) {
+                    if (p >= a.nterm) break;
+                    const bool drude = a.coef[kCoefHead + kCoefMode * p + 5] != 0.0;
+                    pc[p] = (double)Pc_[(long long)p * a.mcells + m];
+                    pp[p] = drude ? 0.0 : (double)Pn_[(long long)p * a.mcells + m];
+                    dsum += pc[p] - pp[p];
+                }
+                En = Eo + R.inv_eps * (a.dt * curl - dsum) - srcterm;
+#pragma unroll
+                for (int p = 0; p < kMaxTerms; ++p) {
+                    if (p >= a.nterm) break;
+                    const double *t = a.coef + kCoefHead + kCoefMode * p;
+                    const bool drude = t[5] != 0.0;
+                    Pn_[(long long)p * a.mcells + m] =
+                        (T)(drude ? t[0] * En + t[1] * pc[p] : t[0] * t[6] * En - t[1] * pc[p] - t[2] * pp[p]);
+                    if (ENERGY && sample) {
+                        const double v = (pc[p] - pp[p]) / a.dt;
+                        ep += 0.5 * t[3] * (v * v + t[4] * pc[p] * pp[p]);
+                    }
+                }
+                if (ENERGY && sample) ef += 0.5 / R.inv_eps * Eo * En;
             } else {  // K_BATH (NG == 0: plain Lorentz)
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
                 T *Pn_ = static_cast<T *>(a.Pnew[c]);
@@ -682,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
 // Lorentz-Bath E update, one (component, cell) per thread: the same arithmetic as the load-first
 // kernel above, for 3D baths whose three components' levels do not fit one thread's registers at
 // a useful occupancy (components x groups > 6).  Blocks are component-major, so the waves of a
-// block stream one component's arrays; within a component each XCD takes a contiguous share.
+// block stream one component's arrays.
 // ---------------------------------------------------------------------------------------------
 template <typename T, int NG, int C>
 __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG> &cf, int t) {
@@ -738,9 +768,11 @@ __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG
 
 template <typename T, int NG>
 __global__ __launch_bounds__(kBlock) void k_update_e_bath_c(const EArgs a, const BathCoef<NG> cf) {
+    // blocks in launch order within a component (every XCD streaming next to the others): on the 512^3
+    // layer 6.30 ms against 6.33 ms with a contiguous share of the component per XCD
     const int nbc = gridDim.x / 3;                  // blocks per component
     const int c = blockIdx.x / nbc;
-    const int t = xcd_block(blockIdx.x - c * nbc, nbc) * kBlock + threadIdx.x;
+    const int t = (blockIdx.x - c * nbc) * kBlock + threadIdx.x;
     if (t >= a.ext[0] * a.ext12) return;
     if (c == 0) bath_component<T, NG, 0>(a, cf, t);
     else if (c == 1) bath_component<T, NG, 1>(a, cf, t);
@@ -805,9 +837,11 @@ struct Cell4 {
     int row;               // region-local row (x, y) of a 3D cell
     bool live;
 };
+// Blocks in launch order, every XCD streaming next to the others: on the 512^3 grid the H pass took
+// 1.02 ms against 1.06 ms, the background E pass 0.818 against 0.830 ms, with a contiguous share per XCD.
 template <class A>
 __device__ __forceinline__ const RegionDesc &v4_region(const A &a, Cell4 &c) {
-    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int b = blockIdx.x;
     int r = -1;
 #pragma unroll
     for (int s = 0; s < kMaxGroup; ++s) r += b >= a.rd->block0[s];
@@ -1439,6 +1473,7 @@ static hipError_t launch_e_dim(const EArgs &a, const double *ch, int kind, int n
         return pml ? launch_e_pml<DIM, T, K_BACKGROUND, 0, true>(a, ch, energy, s)
                    : launch_e_pml<DIM, T, K_BACKGROUND, 0, false>(a, ch, energy, s);
     if (kind == K_DRUDE) return launch_e_pml<DIM, T, K_DRUDE, 0, false>(a, ch, energy, s);
+    if (kind == K_MULTI) return launch_e_pml<DIM, T, K_MULTI, 0, false>(a, ch, energy, s);
     if (kind == K_CLOSURE) {
         const long long n = (long long)a.ext[0] * a.ext12;
         if (n == 0) return hipSuccess;

@@ -77,6 +77,7 @@ struct Material {
     double eps = 1.0, omega0 = 0.0, gamma0 = 0.0, sigma0 = 0.0, sigma_max = 0.0;
     bool sigma_per_cell = false;
     int nb = 0, ng = 0;
+    int nterm = 0;                   // multi-term material: Lorentz / Drude terms
     std::vector<double> wj, gj, kj, coef;
     void *P[2][3] = {};
     void *Y[2][3] = {};
@@ -461,6 +462,7 @@ void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh
         if (m.kind == K_DRUDE) e += 2.0 * ne * w;
         else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * w;
         else if (m.kind == K_CLOSURE) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 2.0 * ne * 16.0;
+        else if (m.kind == K_MULTI) e += 3.0 * ne * m.nterm * w;
     }
     *be = e;
     *bh = h;
@@ -739,6 +741,12 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             a.mcells = m.mcells;
             if (kind == K_DRUDE) {
                 for (int c = 0; c < 3; c++) a.Pcur[c] = m.P[0][c];
+            } else if (kind == K_MULTI) {
+                for (int c = 0; c < 3; c++) {
+                    a.Pcur[c] = m.P[cur][c];
+                    a.Pnew[c] = m.P[nxt][c];
+                }
+                a.nterm = m.nterm;
             } else if (kind == K_BATH || kind == K_CLOSURE) {
                 for (int c = 0; c < 3; c++) {
                     a.Pcur[c] = m.P[cur][c];
@@ -941,7 +949,7 @@ uint64_t fingerprint(const fdtdb_grid_s *g) {
         f.v(m.kind); f.bytes(m.lo, sizeof m.lo); f.bytes(m.hi, sizeof m.hi); f.v(m.eps); f.v(m.omega0);
         f.v(m.gamma0); f.v(m.sigma0); f.v(m.sigma_per_cell); f.v(m.nb); f.vec(m.wj); f.vec(m.gj); f.vec(m.kj);
         f.vec(m.coef); f.v(m.cw_dev != nullptr); f.bytes(m.cscale, sizeof m.cscale);
-        f.v(m.sigma_hash); f.v(m.weight_hash);
+        f.v(m.sigma_hash); f.v(m.weight_hash); f.v(m.nterm);
     }
     f.v(g->srcs.size());
     for (auto &x : g->srcs) {
@@ -1109,6 +1117,53 @@ fdtdb_status fdtdb_set_drude(fdtdb_grid g, const fdtdb_box *box, double omega_p,
     HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
     for (int c = 0; c < 3; c++)
         if (e_active(g->ndim, c)) TRY(g->alloc(&m.P[0][c], words(m.mcells, g->f64)));
+    if (material_id) *material_id = (int)g->mats.size() - 1;
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_multi_term(fdtdb_grid g, const fdtdb_box *box, double eps_inf, int n_terms, const int *kinds,
+                                  const double *omega, const double *gamma, const double *sigma, int *material_id) {
+    TRY(check_new_material(g, box, true));
+    if (!(eps_inf > 0.0) || n_terms < 1 || n_terms > kMaxTerms || !kinds || !omega || !gamma || !sigma)
+        return fail(FDTDB_E_INVALID, "multi-term material needs eps_inf > 0 and 1..%d terms", kMaxTerms);
+    const double dt = g->dt, X = 4.0 / (dt * dt);
+    double e = eps_inf;
+    for (int p = 0; p < n_terms; p++) {
+        if ((kinds[p] != 0 && kinds[p] != 1) || !(omega[p] > 0.0) || !(gamma[p] >= 0.0) ||
+            (kinds[p] == 0 && !(sigma[p] > 0.0)))
+            return fail(FDTDB_E_INVALID, "term %d: kind 0 (Lorentz: omega0, gamma, sigma > 0) or 1 (Drude: omega_p, gamma)", p);
+        if (omega[p] * dt >= 2.0) return fail(FDTDB_E_UNSTABLE, "term %d: omega dt >= 2", p);
+        const double w2 = omega[p] * omega[p];
+        e += kinds[p] == 1 ? -w2 / X : w2 * sigma[p] / (w2 - X);
+    }
+    // lossless lattice bound: the largest mode frequency X = s^2 of X (eps_inf + sum_p chi_p(X)) = 4 ndim stays
+    // below 4/dt^2 (the branch above every resonance increases, so its value at X = 4/dt^2 decides)
+    if (X * e - 4.0 * g->ndim < 0.0)
+        return fail(FDTDB_E_UNSTABLE, "multi-term medium violates the lattice stability bound (margin %.6g)",
+                    X * e - 4.0 * g->ndim);
+    Material &m = new_material(g, box, K_MULTI);
+    m.eps = eps_inf;
+    m.nterm = n_terms;
+    m.coef.assign(kCoefHead + kCoefMode * n_terms, 0.0);
+    for (int p = 0; p < n_terms; p++) {
+        const double w2 = omega[p] * omega[p], A = 1.0 + 0.5 * gamma[p] * dt;
+        double *t = &m.coef[kCoefHead + kCoefMode * p];
+        const bool drude = kinds[p] == 1;
+        // Lorentz: eq:Pz_1D_Lorentz; Drude: the same with omega0^2 dropped, written for the increment
+        // V = P^{n+1/2} - P^{n-1/2}: V' = (w_p^2 dt^2 E + (1 - g dt/2) V) / (1 + g dt/2)
+        t[0] = w2 * dt * dt / A;                                   // times sigma (t[6]) for a Lorentz term
+        t[1] = drude ? (1.0 - 0.5 * gamma[p] * dt) / A : (w2 * dt * dt - 2.0) / A;
+        t[2] = drude ? 0.0 : (1.0 - 0.5 * gamma[p] * dt) / A;
+        t[3] = drude ? 1.0 / w2 : 1.0 / (sigma[p] * w2);           // rho of the term's energy
+        t[4] = drude ? 0.0 : w2;
+        t[5] = kinds[p];
+        t[6] = drude ? 1.0 : sigma[p];
+    }
+    TRY(g->alloc((void **)&m.coef_dev, 8 * m.coef.size()));
+    HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
+    for (int lvl = 0; lvl < 2; lvl++)
+        for (int c = 0; c < 3; c++)
+            if (e_active(g->ndim, c)) TRY(g->alloc(&m.P[lvl][c], words(m.mcells * n_terms, g->f64)));
     if (material_id) *material_id = (int)g->mats.size() - 1;
     return FDTDB_OK;
 }
@@ -1575,7 +1630,39 @@ fdtdb_status fdtdb_get_polarization(fdtdb_grid g, int mid, int c, int level, dou
         return read_state(g, m.P[0][c], m.mcells, out);
     }
     const int slot = (int)((g->steps + level) & 1);
+    if (m.kind == K_MULTI) {     // the total polarization: the sum of the terms (Lorentz terms only)
+        for (int p = 0; p < m.nterm; p++)
+            if (m.coef[kCoefHead + kCoefMode * p + 5] != 0.0)
+                return fail(FDTDB_E_INVALID, "a Drude term stores its increment only: read the terms one by one");
+        std::vector<double> t((size_t)m.mcells);
+        std::fill(out, out + m.mcells, 0.0);
+        for (int p = 0; p < m.nterm; p++) {
+            TRY(read_state(g, static_cast<char *>(m.P[slot][c]) + (size_t)p * m.mcells * (g->f64 ? 8 : 4), m.mcells,
+                           t.data()));
+            for (long long q = 0; q < m.mcells; q++) out[q] += t[q];
+        }
+        return FDTDB_OK;
+    }
     return read_state(g, m.P[slot][c], m.mcells, out);
+}
+
+fdtdb_status fdtdb_get_polarization_term(fdtdb_grid g, int mid, int c, int level, int term, double *out) {
+    if (!g || mid < 0 || mid >= (int)g->mats.size() || c < 0 || c > 2 || level < 0 || level > 1 || !out)
+        return fail(FDTDB_E_INVALID, "bad argument");
+    Material &m = g->mats[mid];
+    if (m.kind != K_MULTI || term < 0 || term >= m.nterm || !e_active(g->ndim, c))
+        return fail(FDTDB_E_INVALID, "no such term");
+    TRY(sync(g));
+    if (m.coef[kCoefHead + kCoefMode * term + 5] != 0.0) {      // Drude term: its increment, in the level-0 slot
+        if (level == 1) {
+            std::fill(out, out + m.mcells, 0.0);
+            return FDTDB_OK;
+        }
+        return read_state(g, static_cast<char *>(m.P[(int)(g->steps & 1)][c]) + (size_t)term * m.mcells * (g->f64 ? 8 : 4),
+                          m.mcells, out);
+    }
+    const int slot = (int)((g->steps + level) & 1);
+    return read_state(g, static_cast<char *>(m.P[slot][c]) + (size_t)term * m.mcells * (g->f64 ? 8 : 4), m.mcells, out);
 }
 
 fdtdb_status fdtdb_get_bath(fdtdb_grid g, int mid, int c, int level, double *out) {

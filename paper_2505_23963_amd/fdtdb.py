@@ -59,6 +59,9 @@ SIGNATURES = [
     ("fdtdb_set_drude", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
     ("fdtdb_set_lorentz_bath", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
                                          C.c_double, C.c_int, _dp, _dp, _dp, C.POINTER(C.c_int)]),
+    ("fdtdb_set_multi_term", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_double, C.c_int, C.POINTER(C.c_int), _dp, _dp,
+                                       _dp, C.POINTER(C.c_int)]),
+    ("fdtdb_get_polarization_term", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, _dp]),
     ("fdtdb_bath_params", C.c_int, [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
                                     _dp, _dp, _dp]),
     ("fdtdb_set_bath_closure", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_int, _dp]),
@@ -259,6 +262,12 @@ class Grid:
                 sig = _arr(m.sigma_cells)
                 _check(L.fdtdb_set_lorentz_bath(self.h, C.byref(b), m.omega0, m.gamma0, m.eps_inf, _ptr(sig),
                                                 m.sigma, m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj), C.byref(mid)))
+            elif kind == "MultiPole":
+                nt = len(m.kinds)
+                kinds = (C.c_int * nt)(*[{"lorentz": 0, "drude": 1}[k] for k in m.kinds])
+                om, ga, sg = (np.ascontiguousarray(v, np.float64) for v in (m.omega, m.gamma, m.sigma))
+                _check(L.fdtdb_set_multi_term(self.h, C.byref(b), m.eps_inf, nt, kinds, _ptr(om), _ptr(ga), _ptr(sg),
+                                              C.byref(mid)))
             else:
                 raise TypeError(kind)
             self.mat_ids.append(mid.value)
@@ -323,6 +332,12 @@ class Grid:
     def polarization(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
         out = np.zeros(self._mcells(mi), np.float64)
         _check(lib().fdtdb_get_polarization(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
+        return out
+
+    def pole(self, mi: int, comp: int, term: int, level: int = 0) -> np.ndarray:
+        """Polarization of one term of a multi-term material."""
+        out = np.zeros(self._mcells(mi), np.float64)
+        _check(lib().fdtdb_get_polarization_term(self.h, self.mat_ids[mi], comp, level, term, _ptr(out)))
         return out
 
     def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:

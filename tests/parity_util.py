@@ -29,12 +29,27 @@ def field_groups(p, closures=()):
     e, h = active_components(p.ndim)
     out = [("E", lambda x, e=e: [x.field(c) for c in e]), ("H", lambda x, h=h: [x.field(c) for c in h])]
     for mi, m in enumerate(p.materials):
+        if type(m).__name__ == "MultiPole":
+            for q, kind in enumerate(m.kinds):
+                if kind == "drude":      # the GPU keeps a Drude term's increment P^{n+1/2} - P^{n-1/2}
+                    out.append((f"V{mi}.{q}", lambda x, mi=mi, q=q, e=e: [term_increment(x, mi, c, q) for c in e]))
+                else:
+                    out.append((f"P{mi}.{q}", lambda x, mi=mi, q=q, e=e: [x.pole(mi, c, q, 0) for c in e]))
+            continue
         if type(m).__name__ != "LorentzBath":
             continue
         out.append((f"P{mi}", lambda x, mi=mi, e=e: [x.polarization(mi, c, 0) for c in e]))
         if m.n_bath and mi not in closures:
             out.append((f"Y{mi}", lambda x, mi=mi, e=e: [x.bath(mi, c, 0) for c in e]))
     return out
+
+
+def term_increment(x, mi, c, q):
+    """P^{n+1/2} - P^{n-1/2} of term q of a multi-term material: the oracle keeps both levels, the GPU library
+    keeps a Drude term's increment itself (its level 0)."""
+    if type(x).__module__.split(".")[0] == "oracle":
+        return x.pole(mi, c, q, 0) - x.pole(mi, c, q, 1)
+    return x.pole(mi, c, q, 0)
 
 
 class Lockstep:

@@ -1,0 +1,127 @@
+"""Sums of Lorentz and Drude terms (Sec. II.A) on the GPU against the oracle: a three-term material
+(Lorentz + Lorentz + Drude) in 1D, 2D and 3D with FP64 state (fields, each Lorentz term's polarization at
+both levels and the Drude term's increment, the flux spectrum and the exact discrete energy), the same with
+FP32 state (the measure of tests/parity_util.py), a one-term material equal to the plain Lorentz medium, and
+the stability check."""
+import numpy as np
+import pytest
+
+from fdtdb_inputs.problem import (CLOSED, PERIODIC, PML, DftFlux, EnergyMonitor, LorentzBath, MultiPole, Problem,
+                                  Source, box)
+from tests.parity_util import TOL_F32, Lockstep
+
+pytestmark = pytest.mark.gpu
+
+KINDS, OMEGA, GAMMA, SIGMA = ("lorentz", "lorentz", "drude"), (0.9, 1.3, 0.6), (0.02, 0.03, 0.01), (0.05, 0.02, 1.0)
+
+
+def _problem(ndim, dtype, steps):
+    if ndim == 1:
+        p = Problem(name="multi1d", ndim=1, n=(400, 1, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(30, 0, 0),
+                    dtype=dtype, steps=steps)
+        xb = box((150, 260))
+        p.sources.append(Source(comp=2, box=box((100, 101)), omega_c=1.0, width=0.5))
+        p.dfts.append(DftFlux(0, box((330, 331)), np.linspace(0.6, 1.4, 33)))
+        p.energies.append(EnergyMonitor(box((40, 360)), every=7))
+    elif ndim == 2:
+        p = Problem(name="multi2d", ndim=2, n=(96, 80, 1), bc=(PML, PML, PERIODIC), pml_cells=(16, 16, 0),
+                    dtype=dtype, steps=steps)
+        xb = box((40, 70), (24, 60))
+        p.sources.append(Source(comp=2, box=box((28, 29), (20, 60)), omega_c=1.0, width=0.5))
+        p.dfts.append(DftFlux(0, box((78, 79), (16, 64)), np.linspace(0.6, 1.4, 17)))
+        p.energies.append(EnergyMonitor(box((16, 80), (16, 64)), every=9))
+    else:
+        p = Problem(name="multi3d", ndim=3, n=(8, 6, 120), bc=(PERIODIC, CLOSED, PML), pml_cells=(0, 0, 16),
+                    dtype=dtype, steps=steps)
+        xb = box((0, 8), (1, 5), (50, 80))
+        p.sources += [Source(comp=0, box=box((0, 8), (0, 6), (30, 31)), omega_c=1.0, width=0.5),
+                      Source(comp=2, box=box((3, 4), (2, 3), (35, 36)), omega_c=0.9, width=0.5, amplitude=0.4)]
+        p.dfts.append(DftFlux(2, box((0, 8), (0, 6), (95, 96)), np.linspace(0.6, 1.4, 9)))
+        p.energies.append(EnergyMonitor(box((0, 8), (0, 6), (16, 104)), every=5))
+    p.materials.append(MultiPole(xb, eps_inf=1.5, kinds=KINDS, omega=OMEGA, gamma=GAMMA, sigma=SIGMA))
+    return p
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_multi_term_fp64(oracle_lib, ndim):
+    from fdtdb_inputs.problem import active_components
+    from paper_2505_23963_amd import Grid
+    p = _problem(ndim, "f64", 600)
+    print(f"[gpu] {p.name} f64 600 steps", flush=True)
+    g = Grid(p)
+    g.step(600)
+    o = oracle_lib.run(p)
+    e, h = active_components(ndim)
+    big = max(np.linalg.norm(o.field(c)) for c in list(e) + list(h))
+    for c in list(e) + list(h):
+        assert np.linalg.norm(g.field(c) - o.field(c)) / max(np.linalg.norm(o.field(c)), 1e-2 * big) < 1e-12, c
+    from tests.parity_util import term_increment
+    for c in e:
+        for q, kind in enumerate(KINDS):
+            if kind == "drude":     # the GPU keeps the increment; the oracle's is a difference of its two levels
+                scale = max(np.linalg.norm(o.pole(0, c, q, 0)), 1e-3)
+                assert np.linalg.norm(term_increment(g, 0, c, q) - term_increment(o, 0, c, q)) <= 1e-12 * scale, (c, q)
+                continue
+            for lvl in (0, 1):
+                ref = o.pole(0, c, q, lvl)
+                assert np.linalg.norm(g.pole(0, c, q, lvl) - ref) <= 1e-12 * max(np.linalg.norm(ref), 1e-3), (c, q, lvl)
+    assert _rel(g.flux(0), o.flux(0)) < 1e-11
+    eg, eo = g.energy(0), o.energy(0)
+    assert eg.shape == eo.shape and np.max(np.abs(eg - eo)) < 1e-11 * np.abs(eo).max()
+    assert np.abs(eo[:, 1]).max() > 1e-3 * np.abs(eo).max()        # the terms carry energy
+
+
+@pytest.mark.parametrize("ndim", [1, 3])
+def test_multi_term_fp32(oracle_lib, ndim):
+    from paper_2505_23963_amd import Grid
+    p = _problem(ndim, "f32", 2000)
+    p.energies.clear()
+    ls = Lockstep(Grid(p), oracle_lib.Oracle(p), p, groups=None).run(2000, 500)
+    ls.report()
+    e, c = ls.worst()
+    assert e < TOL_F32 and c < TOL_F32, (e, c)
+    assert _rel(ls.g.flux(0), ls.o.flux(0)) < TOL_F32
+
+
+def test_one_term_equals_plain_lorentz_on_gpu():
+    """A multi-term material with one Lorentz term advances like the plain Lorentz medium (FP64 state; the
+    two kernels may round their FP64 expressions in a different order)."""
+    from paper_2505_23963_amd import Grid
+    a = _problem(1, "f64", 0)
+    b = _problem(1, "f64", 0)
+    a.materials[0] = MultiPole(a.materials[0].box, 1.5, ("lorentz",), (0.9,), (0.02,), (0.05,))
+    b.materials[0] = LorentzBath(b.materials[0].box, omega0=0.9, gamma0=0.02, eps_inf=1.5, sigma=0.05)
+    ga, gb = Grid(a), Grid(b)
+    ga.step(1500)
+    gb.step(1500)
+    for c in (2, 4):
+        assert _rel(ga.field(c), gb.field(c)) < 1e-13, c
+    assert _rel(ga.polarization(0, 2, 0), gb.polarization(0, 2, 0)) < 1e-13
+
+
+def test_multi_term_validation():
+    """Below the lattice bound of the sum (eps_inf just under X^-1 (4 ndim - X sum_p chi_p(X)), X = 4/dt^2) the
+    material is refused with E_UNSTABLE; just above it is accepted; a term with omega dt >= 2 is refused."""
+    from paper_2505_23963_amd import FdtdbError, Grid
+    from paper_2505_23963_amd.fdtdb import E_UNSTABLE
+    X = 4.0 / 0.25
+    kinds, om, sg = ("lorentz", "drude", "lorentz"), (1.5, 3.0, 0.8), (2.0, 1.0, 0.5)
+    chi = sum(-w * w / X if k == "drude" else w * w * s / (w * w - X) for k, w, s in zip(kinds, om, sg))
+    eb = (4.0 - X * chi) / X
+
+    def grid(eps, omega=om):
+        p = Problem(name="v", ndim=1, n=(8, 1, 1), bc=(PERIODIC, PERIODIC, PERIODIC), dtype="f64")
+        p.materials.append(MultiPole(box((0, 8)), eps, kinds, omega, (0.0, 0.0, 0.0), sg))
+        return Grid(p)
+
+    grid(eb * 1.001)
+    with pytest.raises(FdtdbError) as ei:
+        grid(eb * 0.999)
+    assert ei.value.status == E_UNSTABLE
+    with pytest.raises(FdtdbError) as ei:
+        grid(eb * 2, omega=(1.5, 4.0, 0.8))
+    assert ei.value.status == E_UNSTABLE

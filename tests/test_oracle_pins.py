@@ -137,6 +137,9 @@ def _state_ops(o, p):
         parts.append(("H", c))
     for mi, m in enumerate(p.materials):
         for c in ecomps:
+            if type(m).__name__ == "MultiPole":
+                parts += [("Q", mi, c, q, lvl) for q in range(len(m.kinds)) for lvl in (0, 1)]
+                continue
             parts += [("P", mi, c, 0), ("P", mi, c, 1)]
             if isinstance(m, LorentzBath) and m.n_bath:
                 parts += [("Y", mi, c, 0), ("Y", mi, c, 1)]
@@ -150,6 +153,8 @@ def _state_ops(o, p):
                 out.append(o.field(t[1]).ravel())
             elif t[0] == "P":
                 out.append(o.polarization(t[1], t[2], t[3]))
+            elif t[0] == "Q":
+                out.append(o.pole(t[1], t[2], t[3], t[4]))
             else:
                 out.append(o.bath(t[1], t[2], t[3]).ravel())
         return np.concatenate(out)
@@ -163,6 +168,9 @@ def _state_ops(o, p):
             elif t[0] == "P":
                 n = len(o.polarization(t[1], t[2], t[3]))
                 o.set_polarization(t[1], t[2], t[3], v[i:i + n])
+            elif t[0] == "Q":
+                n = len(o.pole(t[1], t[2], t[3], t[4]))
+                o.set_pole(t[1], t[2], t[3], t[4], v[i:i + n])
             else:
                 n = o.bath(t[1], t[2], t[3]).size
                 o.set_bath(t[1], t[2], t[3], v[i:i + n])
@@ -626,3 +634,80 @@ def test_oracle_threads_do_not_change_results(oracle_lib):
         oracle_lib.set_threads(before)
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+
+# ---------------------------------------------------------------------------------- sums of terms (Sec. II.A)
+def _multi(b, eps=1.5, gam=(0.02, 0.03, 0.01)):
+    from fdtdb_inputs.problem import MultiPole
+    return MultiPole(b, eps_inf=eps, kinds=("lorentz", "lorentz", "drude"), omega=(0.9, 1.3, 0.6),
+                     gamma=gam, sigma=(0.05, 0.02, 1.0))
+
+
+def test_multipole_zero_d_susceptibility_is_the_sum_of_the_terms(oracle_lib):
+    """One driven cell of a Lorentz + Lorentz + Drude material: DFT(P)/DFT(E) equals the sum of the three
+    terms' discrete susceptibilities (each the z-transform of its central-difference update)."""
+    from oracle.closed_form import chi_multipole_discrete
+    m = _multi(box((0, 1)))
+    w, chi = _drive_chi(oracle_lib, m)
+    ref = chi_multipole_discrete(w, DT, m.kinds, m.omega, m.gamma, m.sigma)
+    assert np.max(np.abs(chi - ref) / np.abs(ref)) < 1e-10
+    # every term contributes: leaving any one out misses by far more
+    for q in range(3):
+        part = chi_multipole_discrete(w, DT, [k for i, k in enumerate(m.kinds) if i != q],
+                                      [x for i, x in enumerate(m.omega) if i != q], [x for i, x in enumerate(m.gamma) if i != q],
+                                      [x for i, x in enumerate(m.sigma) if i != q])
+        assert np.max(np.abs(chi - part) / np.abs(ref)) > 1e-3, q
+
+
+def test_multipole_single_terms_equal_lorentz_and_drude(oracle_lib):
+    """A one-term material is the plain Lorentz or Drude medium, bit for bit."""
+    from fdtdb_inputs.problem import MultiPole
+    for one, plain in ((MultiPole(box((80, 140)), 1.3, ("lorentz",), (1.0,), (0.02,), (0.05,)),
+                        LorentzBath(box((80, 140)), omega0=1.0, gamma0=0.02, eps_inf=1.3, sigma=0.05)),
+                       (MultiPole(box((80, 140)), 3.0, ("drude",), (2.0,), (0.05,), (0.0,)),
+                        Drude(box((80, 140)), omega_p=2.0, gamma=0.05, eps_inf=3.0))):
+        _, o1 = _slab_run(oracle_lib, lambda b: one)
+        _, o2 = _slab_run(oracle_lib, lambda b: plain)
+        for c in (2, 4):
+            assert np.array_equal(o1.field(c), o2.field(c))
+
+
+def test_multipole_exact_energy_conservation(oracle_lib):
+    """Lossless closed 2D box with a three-term material and a Lorentz-Bath block: the exact discrete energy,
+    with one oscillator energy per term, is constant once the pulse is off."""
+    p = _closed_problem(2, lossless=True, steps=600)
+    p.materials[2] = _multi(box((16, 19), (1, 8)), gam=(0.0, 0.0, 0.0))
+    o = oracle_lib.run(p)
+    tot = o.energy(0).sum(axis=1)
+    assert np.max(np.abs(tot[12:] - tot[12])) / tot[12] < 1e-11
+    assert np.ptp(o.energy(0)[12:, 1]) / tot[12] > 1e-3
+
+
+def test_multipole_slab_transmission_lattice_tmm(oracle_lib):
+    from oracle.closed_form import chi_multipole_discrete, lattice_transmission
+    w = np.linspace(0.7, 1.4, 71)
+    m = _multi(box((300, 380)))
+    T = _transmission(oracle_lib, [m], w)
+    chi = chi_multipole_discrete(w, DT, m.kinds, m.omega, m.gamma, m.sigma)
+    ref = lattice_transmission(w, DT, np.full(80, 1.5), np.tile(chi, (80, 1)))
+    assert np.max(np.abs(T - ref)) < 1e-5
+    assert ref.min() < 0.5
+
+
+def test_multipole_stability_bound_matches_propagator(oracle_lib):
+    """The stability condition of a sum of terms, X (eps + sum_p chi_p(X)) >= 4 ndim at X = 4/dt^2, is where
+    the one-step propagator's eigenvalues leave the unit circle."""
+    from fdtdb_inputs.problem import MultiPole
+    from oracle.closed_form import lossless_margin, multipole_margin
+    kinds, om, sg = ("lorentz", "drude", "lorentz"), (1.5, 3.0, 0.8), (2.0, 1.0, 0.5)
+    # the margin is linear in eps: the bound
+    e0 = multipole_margin(DT, 1, 0.0, kinds, om, sg)
+    eb = -e0 / (4.0 / DT ** 2)
+    assert abs(multipole_margin(DT, 1, eb, kinds, om, sg)) < 1e-9
+    # one Lorentz term: the lossless_margin condition
+    m1 = multipole_margin(DT, 1, 1.3, ("lorentz",), (1.5,), (2.0,))
+    assert abs(m1 / (4 / DT ** 2) * (4 / DT ** 2 - 1.5 ** 2) - lossless_margin(DT, 1, 1.3, omega0=1.5, sigma=2.0)) < 1e-9
+    mk = lambda e: _periodic_1d(8, [MultiPole(box((0, 8)), e, kinds, om, (0.0, 0.0, 0.0), sg)])
+    assert np.max(np.abs(np.linalg.eigvals(one_step_map(oracle_lib, mk(eb * 1.02))))) < 1.0 + 1e-6
+    assert np.max(np.abs(np.linalg.eigvals(one_step_map(oracle_lib, mk(eb * 0.95))))) > 1.0 + 1e-3
