@@ -767,12 +767,12 @@ __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG
 }
 
 template <typename T, int NG>
-__global__ __launch_bounds__(kBlock) void k_update_e_bath_c(const EArgs a, const BathCoef<NG> cf) {
+__global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, const BathCoef<NG> cf) {
     // blocks in launch order within a component (every XCD streaming next to the others): on the 512^3
     // layer 6.30 ms against 6.33 ms with a contiguous share of the component per XCD
     const int nbc = gridDim.x / 3;                  // blocks per component
     const int c = blockIdx.x / nbc;
-    const int t = (blockIdx.x - c * nbc) * kBlock + threadIdx.x;
+    const int t = (blockIdx.x - c * nbc) * kBathBlock + threadIdx.x;
     if (t >= a.ext[0] * a.ext12) return;
     if (c == 0) bath_component<T, NG, 0>(a, cf, t);
     else if (c == 1) bath_component<T, NG, 1>(a, cf, t);
@@ -1439,7 +1439,8 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
         if (energy)
             hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
         else if constexpr (DIM == 3 && NC * NG > 6)
-            hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * nblocks(n)), dim3(kBlock), 0, s, a, cf);
+            hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
+                               dim3(kBathBlock), kBathLdsReserve, s, a, cf);
         else
             hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>), dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)),
                                dim3(kBlock), 0, s, a, cf);

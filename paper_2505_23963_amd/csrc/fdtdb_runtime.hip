@@ -204,22 +204,31 @@ struct fdtdb_grid_s {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
 
+    std::map<void *, void *> bases;   // allocations handed out at an offset: their start
     DevAllocator mem = current_allocator();
-    fdtdb_status alloc(void **p, size_t bytes) {
+    // bytes of device memory, zeroed; offset > 0 (a multiple of 256) hands out the memory that many
+    // bytes past the start of the allocation
+    fdtdb_status alloc(void **p, size_t bytes, size_t offset = 0) {
         if (bytes == 0) bytes = 8;
-        hipError_t e = dev_alloc(mem, p, bytes);
+        void *b = nullptr;
+        hipError_t e = dev_alloc(mem, &b, bytes + offset);
         if (e != hipSuccess) return fail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
-        e = hipMemset(*p, 0, bytes);
+        e = hipMemset(b, 0, bytes + offset);
         if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
-        allocs.push_back(*p);
+        allocs.push_back(b);
+        *p = static_cast<char *>(b) + offset;
+        if (offset) bases[*p] = b;
         sizes[*p] = bytes;
         return FDTDB_OK;
     }
     void release(void *&p) {
         if (!p) return;
         sizes.erase(p);
+        auto it = bases.find(p);
+        void *b = it == bases.end() ? p : it->second;
+        if (it != bases.end()) bases.erase(it);
         for (auto &q : allocs)
-            if (q == p) {
+            if (q == b) {
                 dev_free(mem, q);
                 q = allocs.back();
                 allocs.pop_back();
@@ -1255,7 +1264,10 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
         for (int c = 0; c < 3; c++) {
             if (!e_active(g->ndim, c)) continue;
             TRY(g->alloc(&m.P[lvl][c], words(mc, g->f64)));
-            if (ng) TRY(g->alloc(&m.Y[lvl][c], words(mc * 4 * ng, g->f64)));
+            // the six bath-level arrays are handed out 0, 1, ..., 5 KiB into their allocations (which
+            // start on the same large-page boundary): the 512^3 layer's bath launch took 6.26 ms
+            // against 6.33 ms with every array at the start of its allocation
+            if (ng) TRY(g->alloc(&m.Y[lvl][c], words(mc * 4 * ng, g->f64), 1024 * (size_t)(3 * lvl + c)));
         }
     if (material_id) *material_id = (int)g->mats.size() - 1;
     return FDTDB_OK;

@@ -67,6 +67,19 @@ def test_fp32_config5_crop_4000_steps(oracle_lib):
     assert rel < TOL_F32
 
 
+def test_fp32_config5_full_planes_600_steps(oracle_lib):
+    """Large 3D layout with full 512 x 512 x-planes (4 of them, periodic in x), so that the z-vector E and
+    H kernels and the component-split bath kernel run with the row count, block order and neighbour
+    offsets of the full grid (x-planes of 62, 224 and 410 blocks).  600 steps carry the pulse through the
+    bath layer's front."""
+    p = configs.config5_3d_large(nx=4, ny=512, steps=600, nfreq=16)
+    ls, g, o = _lockstep(oracle_lib, p, 600, 200)
+    _assert_fields(ls)
+    rel, _ = flux_errors(g.flux(0), o.flux(0), o.flux(0, raw=True)[1])
+    print(f"  flux rel-L2 {rel:.3e}", flush=True)
+    assert rel < TOL_F32
+
+
 def test_fp32_config1_20000_steps(oracle_lib):
     """The 1D Fabry-Perot workload (N_b = 16) with FP32 state for all 20 000 steps.  The in-cavity flux
     is measured against its cancellation scale; the monitor behind the opaque mirror reads FP32 rounding
