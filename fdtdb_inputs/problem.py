@@ -90,6 +90,7 @@ class Source:
     width: float
     amplitude: float = 1.0
     profile: Optional[np.ndarray] = None          # per cell of the box
+    profile_im: Optional[np.ndarray] = None       # Bloch grids: imaginary part of a complex profile
 
 
 @dataclass
@@ -120,6 +121,9 @@ class Problem:
     dfts: List[DftFlux] = field(default_factory=list)
     energies: List[EnergyMonitor] = field(default_factory=list)
     steps: int = 100
+    # Bloch phases phi_a = k_a n_a (radians) of the periodic axes: the fields become complex with
+    # f(r + n_a e_a) = exp(i phi_a) f(r); None keeps real fields (plain periodic axes)
+    bloch: Optional[Tuple[float, float, float]] = None
 
     @property
     def cells(self) -> int:

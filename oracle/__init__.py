@@ -62,6 +62,7 @@ def lib():
         L.or_add_dft.argtypes = [C.c_void_p, C.c_int, _lp, _lp, C.c_int, _dp]
         L.or_add_energy.argtypes = [C.c_void_p, _lp, _lp, C.c_int]
         L.or_step.argtypes = [C.c_void_p, C.c_long]
+        L.or_pair_bloch.argtypes = [C.c_void_p, C.c_void_p, _dp]
         L.or_get_step.restype = C.c_long
         L.or_get_step.argtypes = [C.c_void_p]
         L.or_set_threads.restype = C.c_int
@@ -111,26 +112,47 @@ def bath_arrays(mat):
 
 
 class Oracle:
-    """One FP64 grid on the CPU, set up from a workload description."""
+    """One FP64 grid on the CPU, set up from a workload description.  A problem with Bloch phases
+    (problem.bloch) holds two grids, the real and imaginary parts of the complex fields (gi is the
+    imaginary part's grid); fields, polarizations and bath coordinates then read back complex, the
+    flux is that of the complex fields and the energies are the sums over both parts."""
 
     def __init__(self, problem, closures: Optional[Dict[int, dict]] = None):
         self.p = problem
+        self._keep = []
+        self.gi = None
+        self.g = self._make(problem, closures, 0)
+        if problem.bloch is not None:
+            if closures:
+                raise ValueError("oracle: learned closures on Bloch grids are not supported")
+            self.gi = self._make(problem, None, 1)
+            ph = np.ascontiguousarray(problem.bloch, np.float64)
+            if lib().or_pair_bloch(self.g, self.gi, ph) != 0:
+                raise ValueError("oracle: bad Bloch phases (periodic axes only)")
+
+    def _make(self, problem, closures, part: int):
+        """One grid with the problem's set-up; part 1 (imaginary part of a Bloch grid) takes the
+        imaginary parts of the source profiles (sources without one are real and drive part 0 only)."""
         L = lib()
         n = problem.n
-        self.g = L.or_create(problem.ndim, n[0], n[1], n[2], problem.courant)
-        if not self.g:
+        g = L.or_create(problem.ndim, n[0], n[1], n[2], problem.courant)
+        if not g:
             raise ValueError("oracle: bad grid")
-        self._keep = []
         for a in range(problem.ndim):
-            L.or_set_boundary(self.g, a, int(problem.bc[a]), int(problem.pml_cells[a]), float(problem.pml_R0))
+            L.or_set_boundary(g, a, int(problem.bc[a]), int(problem.pml_cells[a]), float(problem.pml_R0))
+        self._setup(g, problem, closures, part)
+        return g
+
+    def _setup(self, g, problem, closures, part):
+        L = lib()
         closures = closures or {}
         for mi, m in enumerate(problem.materials):
             lo, hi = _box(m.box)
             kind = type(m).__name__
             if kind == "Dielectric":
-                rc = L.or_add_dielectric(self.g, lo, hi, m.eps_inf)
+                rc = L.or_add_dielectric(g, lo, hi, m.eps_inf)
             elif kind == "Drude":
-                rc = L.or_add_drude(self.g, lo, hi, m.omega_p, m.gamma, m.eps_inf)
+                rc = L.or_add_drude(g, lo, hi, m.omega_p, m.gamma, m.eps_inf)
             elif kind == "LorentzBath":
                 sig = None if m.sigma_cells is None else np.ascontiguousarray(m.sigma_cells, np.float64).ravel()
                 self._keep.append(sig)
@@ -138,16 +160,16 @@ class Oracle:
                     cl = closures[mi]
                     w = np.ascontiguousarray(cl["weights"], np.float64)
                     s = np.ascontiguousarray(cl["scales"], np.float64)
-                    rc = L.or_add_closure(self.g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
+                    rc = L.or_add_closure(g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
                                           float(cl["sum_kc"]), int(cl["width"]), w, s)
                 else:
                     wj, gj, kj = bath_arrays(m)
                     self._keep += [wj, gj, kj]
-                    rc = L.or_add_lorentz_bath(self.g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
+                    rc = L.or_add_lorentz_bath(g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
                                                m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj))
             elif kind == "MultiPole":
                 kinds = np.array([{"lorentz": 0, "drude": 1}[k] for k in m.kinds], np.int32)
-                rc = L.or_add_multipole(self.g, lo, hi, m.eps_inf, len(kinds), kinds,
+                rc = L.or_add_multipole(g, lo, hi, m.eps_inf, len(kinds), kinds,
                                         np.ascontiguousarray(m.omega, np.float64), np.ascontiguousarray(m.gamma, np.float64),
                                         np.ascontiguousarray(m.sigma, np.float64))
             else:
@@ -156,25 +178,34 @@ class Oracle:
                 raise ValueError(f"oracle: material {mi} rejected")
         for s in problem.sources:
             lo, hi = _box(s.box)
-            prof = None if s.profile is None else np.ascontiguousarray(s.profile, np.float64).ravel()
+            pr = s.profile if part == 0 else s.profile_im
+            if part == 1 and pr is None:
+                continue
+            prof = None if pr is None else np.ascontiguousarray(pr, np.float64).ravel()
             self._keep.append(prof)
-            if L.or_add_source(self.g, s.comp, lo, hi, s.omega_c, s.width, s.amplitude, _ptr(prof)) < 0:
+            if L.or_add_source(g, s.comp, lo, hi, s.omega_c, s.width, s.amplitude, _ptr(prof)) < 0:
                 raise ValueError("oracle: bad source")
         for d in problem.dfts:
             lo, hi = _box(d.box)
             om = np.ascontiguousarray(d.omega, np.float64)
-            if L.or_add_dft(self.g, d.axis, lo, hi, len(om), om) < 0:
+            if L.or_add_dft(g, d.axis, lo, hi, len(om), om) < 0:
                 raise ValueError("oracle: bad dft")
         for e in problem.energies:
             lo, hi = _box(e.box)
-            if L.or_add_energy(self.g, lo, hi, e.every) < 0:
+            if L.or_add_energy(g, lo, hi, e.every) < 0:
                 raise ValueError("oracle: bad energy monitor")
 
     def __del__(self):
-        g = getattr(self, "g", None)
-        if g:
-            lib().or_destroy(g)
-            self.g = None
+        for name in ("g", "gi"):
+            g = getattr(self, name, None)
+            if g:
+                lib().or_destroy(g)
+                setattr(self, name, None)
+
+    def _both(self, fn):
+        """fn(grid) of the real part, + 1j fn(grid) of the imaginary part on a Bloch grid"""
+        v = fn(self.g)
+        return v if self.gi is None else v + 1j * fn(self.gi)
 
     def step(self, n: int):
         lib().or_step(self.g, int(n))
@@ -184,20 +215,27 @@ class Oracle:
         return lib().or_get_step(self.g)
 
     def field(self, comp: int) -> np.ndarray:
-        out = np.zeros(self.p.cells, np.float64)
-        lib().or_get_field(self.g, comp, out)
-        return out.reshape(self.p.n)
+        def one(g):
+            out = np.zeros(self.p.cells, np.float64)
+            lib().or_get_field(g, comp, out)
+            return out.reshape(self.p.n)
+        return self._both(one)
 
     def set_field(self, comp: int, values: np.ndarray):
-        lib().or_set_field(self.g, comp, np.ascontiguousarray(values, np.float64).ravel())
+        lib().or_set_field(self.g, comp, np.ascontiguousarray(np.real(values), np.float64).ravel())
+        if self.gi is not None:
+            lib().or_set_field(self.gi, comp, np.ascontiguousarray(np.imag(values), np.float64).ravel())
 
     def polarization(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
         m = self.p.materials[mi]
         nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
-        out = np.zeros(nc, np.float64)
-        if lib().or_get_P(self.g, mi, comp, level, out) != 0:
-            raise ValueError("no polarization")
-        return out
+
+        def one(g):
+            out = np.zeros(nc, np.float64)
+            if lib().or_get_P(g, mi, comp, level, out) != 0:
+                raise ValueError("no polarization")
+            return out
+        return self._both(one)
 
     def pole(self, mi: int, comp: int, pole: int, level: int = 0) -> np.ndarray:
         """Polarization of one term of a multi-term material."""
@@ -215,10 +253,13 @@ class Oracle:
     def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
         m = self.p.materials[mi]
         nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
-        out = np.zeros(m.n_bath * nc, np.float64)
-        if lib().or_get_Y(self.g, mi, comp, level, out) != 0:
-            raise ValueError("no bath")
-        return out.reshape(m.n_bath, nc)
+
+        def one(g):
+            out = np.zeros(m.n_bath * nc, np.float64)
+            if lib().or_get_Y(g, mi, comp, level, out) != 0:
+                raise ValueError("no bath")
+            return out.reshape(m.n_bath, nc)
+        return self._both(one)
 
     def set_polarization(self, mi: int, comp: int, level: int, values: np.ndarray):
         if lib().or_set_P(self.g, mi, comp, level, np.ascontiguousarray(values, np.float64).ravel()) != 0:
@@ -253,15 +294,27 @@ class Oracle:
         lib().or_get_dft(self.g, mid, out, _ptr(r))
         if raw:
             rr = r.reshape(4, npts, nf, 2)
-            return out, rr[..., 0] + 1j * rr[..., 1]
+            tr = rr[..., 0] + 1j * rr[..., 1]
+            if self.gi is not None:   # transforms of the complex fields: real part's + 1j * imaginary part's
+                ri = np.zeros(4 * npts * nf * 2, np.float64)
+                lib().or_get_dft(self.gi, mid, np.zeros(nf, np.float64), _ptr(ri))
+                ri = ri.reshape(4, npts, nf, 2)
+                tr = tr + 1j * (ri[..., 0] + 1j * ri[..., 1])
+            return out, tr
         return out
 
     def energy(self, mid: int) -> np.ndarray:
-        n = lib().or_energy_count(self.g, mid)
-        out = np.zeros(3 * max(n, 0), np.float64)
-        if n > 0:
-            lib().or_get_energy(self.g, mid, out)
-        return out.reshape(-1, 3)
+        """[field, polarization, bath] per sample (summed over both parts of a Bloch grid)"""
+        tot = None
+        for g in (self.g, self.gi):
+            if g is None:
+                continue
+            n = lib().or_energy_count(g, mid)
+            out = np.zeros(3 * max(n, 0), np.float64)
+            if n > 0:
+                lib().or_get_energy(g, mid, out)
+            tot = out.reshape(-1, 3) if tot is None else tot + out.reshape(-1, 3)
+        return tot
 
 
 def run(problem, steps: Optional[int] = None, closures=None) -> Oracle:

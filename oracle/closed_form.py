@@ -131,18 +131,32 @@ def phase_velocity(w, dt):
     return np.asarray(w) / lattice_k(w, dt)
 
 
-def lattice_transmission(w, dt, eps_cells, chi_cells):
+def lattice_transmission(w, dt, eps_cells, chi_cells, ky: float = 0.0):
     """|t|^2 of a 1D layer stack on the Yee lattice, vacuum on both sides.
 
     The lattice Helmholtz equation E_{j+1} - 2E_j + E_{j-1} + s2 (eps_j + chi_j) E_j = 0
     is integrated from a pure transmitted wave exp(i k j) behind the stack back
     to the front, where the field splits into incident and reflected lattice
     plane waves.  eps_cells: (L,) background; chi_cells: (L, nw) complex.
+
+    ky != 0: the 2D TM lattice (E_z) with every field proportional to exp(i ky y) (oblique incidence
+    on a Bloch-periodic grid): the y second difference contributes -4 sin^2(ky/2) E_j, so s2 (eps + chi)
+    becomes s2 (eps + chi) - 4 sin^2(ky/2) and the vacuum wavenumber along x solves
+    4 sin^2(k/2) = s2 - 4 sin^2(ky/2).
     """
     w = np.atleast_1d(np.asarray(w, dtype=np.float64))
     L = len(eps_cells)
     k = lattice_k(w, dt)
     S2 = s2(w, dt)
+    if ky != 0.0:
+        ty = 4.0 * np.sin(ky / 2.0) ** 2
+        k = 2.0 * np.arcsin(np.sqrt(S2 - ty) / 2.0)
+        eps_cells = np.asarray(eps_cells, dtype=np.float64)
+        # s2 (eps + chi) - ty = s2 (eps + chi - ty / s2): fold the transverse term into chi
+        chi_cells = np.asarray(chi_cells, dtype=np.complex128) - ty / S2
+        S2v = S2 - ty
+    else:
+        S2v = S2
     # cells L, L+1 are vacuum, carrying exp(i k j)
     e_next = np.exp(1j * k * (L + 1))
     e_cur = np.exp(1j * k * L)
@@ -155,7 +169,7 @@ def lattice_transmission(w, dt, eps_cells, chi_cells):
         if 0 <= node < L:
             fac = 2.0 - S2 * (eps_cells[node] + chi_cells[node])
         else:
-            fac = 2.0 - S2
+            fac = 2.0 - S2v
         e_prev = fac * e_cur - e_next
         e_next, e_cur = e_cur, e_prev
         big = np.maximum(np.abs(e_cur), np.abs(e_next))

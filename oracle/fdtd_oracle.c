@@ -37,6 +37,15 @@
  *
  * Boundaries per axis: periodic (wrap), closed (field values beyond the
  * grid read as zero), or CPML (closed, with a graded absorbing layer).
+ *
+ * Bloch-periodic axes (the boundary condition the paper applies along y in
+ * its 2D runs, Appendix "Simulation details", here with any phase): the
+ * field is complex and obeys f(r + L e_a) = exp(i phi_a) f(r), phi_a = k_a L.
+ * Every update has real coefficients, so the real and imaginary parts are
+ * two real grids of identical set-up (or_pair_bloch) that meet only where a
+ * neighbour read crosses a Bloch axis: there part p of exp(+-i phi) (R + i I)
+ * is read.  Sources of the imaginary part carry the imaginary part of a
+ * complex profile; the flux is Re sum (E~ x conj H~) of the complex DFTs.
  * CPML is the convolutional PML of Roden and Gedney (2000) with kappa = 1,
  * alpha = 0: psi <- b psi + (b - 1) dF, b = exp(-s dt), and the derivative dF
  * is replaced by dF + psi.  The grading is s(d) = s_max (d/L)^3 with
@@ -104,7 +113,7 @@ typedef struct {
     double *out;                      /* [sample][field, P, bath] */
 } Energy;
 
-typedef struct {
+typedef struct Grid {
     int ndim;
     long n[3], ncell;
     double dt;
@@ -118,6 +127,10 @@ typedef struct {
     double *sE[3], *sH[3];            /* CPML conductivity per axis, E- and H-type nodes */
     double *psiE[3][3], *psiH[3][3];  /* [component][derivative axis] */
     long step;
+    /* Bloch pair: the other part's grid, this grid's part (0 real, 1 imaginary), phase per axis */
+    struct Grid *twin;
+    int part;
+    double bph[3];
     int nmat, nsrc, ndft, nen;
     Mat m[MAXMAT];
     Src s[MAXSRC];
@@ -127,16 +140,28 @@ typedef struct {
 
 static long IDX(const Grid *g, long i, long j, long k) { return (i * g->n[1] + j) * g->n[2] + k; }
 
-/* field value at (i,j,k) with the boundary rule of each axis */
-static double at(const Grid *g, const double *f, long i, long j, long k) {
+enum { F_E = 0, F_H = 1 };
+static const double *field_of(const Grid *g, int F, int c) { return F == F_E ? g->E[c] : g->H[c]; }
+
+/* value of field F (E or H), component c, at (i,j,k) with the boundary rule of each axis.  On a Bloch
+ * pair a read past the upper (lower) end of a periodic axis a picks up exp(+i phi_a) (exp(-i phi_a)):
+ * with the own part v and the other part w, part 0 reads Re(e^{i t}(v + i w)) = cos t v - sin t w and
+ * part 1 reads Im(e^{i t}(w + i v)) = cos t v + sin t w. */
+static double at(const Grid *g, int F, int comp, long i, long j, long k) {
+    const double *f = field_of(g, F, comp);
     long c[3] = {i, j, k};
+    double t = 0.0;
     for (int a = 0; a < 3; a++) {
         if (c[a] < 0 || c[a] >= g->n[a]) {
-            if (g->bc[a] == BC_PERIODIC) c[a] = (c[a] % g->n[a] + g->n[a]) % g->n[a];
-            else return 0.0;
+            if (g->bc[a] != BC_PERIODIC) return 0.0;
+            t += (c[a] < 0 ? -1.0 : 1.0) * g->bph[a];
+            c[a] = (c[a] % g->n[a] + g->n[a]) % g->n[a];
         }
     }
-    return f[IDX(g, c[0], c[1], c[2])];
+    long q = IDX(g, c[0], c[1], c[2]);
+    if (!g->twin || t == 0.0) return f[q];
+    double w = field_of(g->twin, F, comp)[q];
+    return g->part == 0 ? cos(t) * f[q] - sin(t) * w : cos(t) * f[q] + sin(t) * w;
 }
 
 static double *zalloc(long n) { return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
@@ -386,20 +411,20 @@ int or_add_energy(void *gp, const long *lo, const long *hi, int every) {
 /* For component c the curl is  d_{a1} F_{f1} - d_{a2} F_{f2}  with (c, a1, a2) cyclic. */
 static const int CYC[3][2] = {{1, 2}, {2, 0}, {0, 1}};
 
-/* backward difference of H along axis a at cell (i,j,k): H(cell) - H(cell - e_a) */
-static double dH(const Grid *g, const double *f, int a, long i, long j, long k) {
-    if (!f) return 0.0;
+/* backward difference of H_comp along axis a at cell (i,j,k): H(cell) - H(cell - e_a) */
+static double dH(const Grid *g, int comp, int a, long i, long j, long k) {
+    if (!g->H[comp]) return 0.0;
     long c[3] = {i, j, k};
     c[a] -= 1;
-    return at(g, f, i, j, k) - at(g, f, c[0], c[1], c[2]);
+    return at(g, F_H, comp, i, j, k) - at(g, F_H, comp, c[0], c[1], c[2]);
 }
 
-/* forward difference of E along axis a: E(cell + e_a) - E(cell) */
-static double dE(const Grid *g, const double *f, int a, long i, long j, long k) {
-    if (!f) return 0.0;
+/* forward difference of E_comp along axis a: E(cell + e_a) - E(cell) */
+static double dE(const Grid *g, int comp, int a, long i, long j, long k) {
+    if (!g->E[comp]) return 0.0;
     long c[3] = {i, j, k};
     c[a] += 1;
-    return at(g, f, c[0], c[1], c[2]) - at(g, f, i, j, k);
+    return at(g, F_E, comp, c[0], c[1], c[2]) - at(g, F_E, comp, i, j, k);
 }
 
 static void update_D(Grid *g) {
@@ -413,8 +438,8 @@ static void update_D(Grid *g) {
             for (long j = 0; j < g->n[1]; j++)
                 for (long k = 0; k < g->n[2]; k++) {
                     long q = IDX(g, i, j, k), pos[3] = {i, j, k};
-                    double t1 = dH(g, g->H[a2], a1, i, j, k);
-                    double t2 = dH(g, g->H[a1], a2, i, j, k);
+                    double t1 = dH(g, a2, a1, i, j, k);
+                    double t2 = dH(g, a1, a2, i, j, k);
                     if (g->psiE[c][a1]) {
                         double b = exp(-g->sE[a1][pos[a1]] * dt);
                         g->psiE[c][a1][q] = b * g->psiE[c][a1][q] + (b - 1.0) * t1;
@@ -582,8 +607,8 @@ static void update_H(Grid *g) {
             for (long j = 0; j < g->n[1]; j++)
                 for (long k = 0; k < g->n[2]; k++) {
                     long q = IDX(g, i, j, k), pos[3] = {i, j, k};
-                    double t1 = g->activeE[a2] ? dE(g, g->E[a2], a1, i, j, k) : 0.0;
-                    double t2 = g->activeE[a1] ? dE(g, g->E[a1], a2, i, j, k) : 0.0;
+                    double t1 = g->activeE[a2] ? dE(g, a2, a1, i, j, k) : 0.0;
+                    double t2 = g->activeE[a1] ? dE(g, a1, a2, i, j, k) : 0.0;
                     if (g->psiH[c][a1]) {
                         double b = exp(-g->sH[a1][pos[a1]] * dt);
                         g->psiH[c][a1][q] = b * g->psiH[c][a1][q] + (b - 1.0) * t1;
@@ -680,7 +705,7 @@ static void accumulate_dft(Grid *g, Dft *d, int fieldE) {
                         if (!g->activeH[c]) continue;
                         long b[3] = {i, j, k};
                         b[d->axis] -= 1;
-                        val = 0.5 * (at(g, g->H[c], b[0], b[1], b[2]) + at(g, g->H[c], i, j, k));
+                        val = 0.5 * (at(g, F_H, c, b[0], b[1], b[2]) + at(g, F_H, c, i, j, k));
                     }
                     double *acc = &d->acc[(((long)(fieldE ? s : 2 + s) * d->npts + p) * d->nf) * 2];
                     for (int f = 0; f < d->nf; f++) {
@@ -692,20 +717,45 @@ static void accumulate_dft(Grid *g, Dft *d, int fieldE) {
             }
 }
 
+/* One step of a grid, or of both parts of a Bloch pair (stepped through part 0): every phase runs on
+ * both parts before the next phase, so that reads across a Bloch axis see the other part at the same
+ * time level. */
 int or_step(void *gp, long nsteps) {
     Grid *g = (Grid *)gp;
-    build_pml(g);
+    if (g->twin && g->part != 0) return -1;
+    Grid *parts[2] = {g, g->twin};
+    int np = g->twin ? 2 : 1;
+    for (int p = 0; p < np; p++) build_pml(parts[p]);
     for (long s = 0; s < nsteps; s++) {
-        update_D(g);
-        update_E(g);
-        for (int e = 0; e < g->nen; e++)
-            if (g->step % g->e[e].every == 0) sample_energy(g, &g->e[e]);
-        for (int mi = 0; mi < g->nmat; mi++) update_material(g, &g->m[mi]);
-        for (int d = 0; d < g->ndft; d++) accumulate_dft(g, &g->d[d], 1);
-        update_H(g);
-        for (int d = 0; d < g->ndft; d++) accumulate_dft(g, &g->d[d], 0);
-        g->step++;
+        for (int p = 0; p < np; p++) update_D(parts[p]);
+        for (int p = 0; p < np; p++) {
+            Grid *h = parts[p];
+            update_E(h);
+            for (int e = 0; e < h->nen; e++)
+                if (h->step % h->e[e].every == 0) sample_energy(h, &h->e[e]);
+            for (int mi = 0; mi < h->nmat; mi++) update_material(h, &h->m[mi]);
+            for (int d = 0; d < h->ndft; d++) accumulate_dft(h, &h->d[d], 1);
+        }
+        for (int p = 0; p < np; p++) update_H(parts[p]);
+        for (int p = 0; p < np; p++) {
+            for (int d = 0; d < parts[p]->ndft; d++) accumulate_dft(parts[p], &parts[p]->d[d], 0);
+            parts[p]->step++;
+        }
     }
+    return 0;
+}
+
+/* Make re and im the real and imaginary parts of one complex grid with Bloch phases phase[a] (radians,
+ * k_a n_a) on its periodic axes.  Both grids must have the same shape and boundaries and must not have
+ * stepped; their materials and monitors are set up alike by the caller.  Returns 0, or -1. */
+int or_pair_bloch(void *rp, void *ip, const double *phase) {
+    Grid *re = (Grid *)rp, *im = (Grid *)ip;
+    if (re == im || re->twin || im->twin || re->step || im->step) return -1;
+    for (int a = 0; a < 3; a++)
+        if (re->n[a] != im->n[a] || re->bc[a] != im->bc[a] || (phase[a] != 0.0 && re->bc[a] != BC_PERIODIC)) return -1;
+    re->twin = im; im->twin = re;
+    re->part = 0; im->part = 1;
+    for (int a = 0; a < 3; a++) re->bph[a] = im->bph[a] = phase[a];
     return 0;
 }
 
@@ -824,20 +874,34 @@ int or_drive_material(void *gp, int mi, int c, const double *e_seq, long n, doub
     return 0;
 }
 
-/* flux[f] = Re sum_p (E~ x conj(H~)) . e_axis ; raw (optional) = [4][npts][nf][2] accumulators */
+/* flux[f] = Re sum_p (E~ x conj(H~)) . e_axis ; raw (optional) = [4][npts][nf][2] accumulators of this
+ * grid (of this part, on a Bloch pair).  On a Bloch pair (asked of part 0) the transforms are those of the
+ * complex fields, E~ = E~_re + i E~_im with E~_re, E~_im the transforms of the two parts' series. */
 int or_get_dft(void *gp, int id, double *flux, double *raw) {
     Grid *g = (Grid *)gp;
     if (id < 0 || id >= g->ndft) return -1;
-    Dft *d = &g->d[id];
+    if (g->twin && g->part != 0) {   /* the imaginary part: its accumulators only */
+        if (!raw) return -1;
+        memcpy(raw, g->d[id].acc, sizeof(double) * 4 * (size_t)g->d[id].npts * (size_t)g->d[id].nf * 2);
+        return 0;
+    }
+    Dft *d = &g->d[id], *di = g->twin ? &g->twin->d[id] : NULL;
     for (int f = 0; f < d->nf; f++) {
         double s = 0.0;
         for (long p = 0; p < d->npts; p++) {
-            const double *e1 = &d->acc[((0 * d->npts + p) * d->nf + f) * 2];
-            const double *e2 = &d->acc[((1 * d->npts + p) * d->nf + f) * 2];
-            const double *h1 = &d->acc[((2 * d->npts + p) * d->nf + f) * 2];
-            const double *h2 = &d->acc[((3 * d->npts + p) * d->nf + f) * 2];
+            double v[4][2];   /* complex transform of E_t1, E_t2, H_t1, H_t2 at this point and frequency */
+            for (int u = 0; u < 4; u++) {
+                const double *r = &d->acc[((u * d->npts + p) * d->nf + f) * 2];
+                v[u][0] = r[0];
+                v[u][1] = r[1];
+                if (di) {   /* + i (transform of the imaginary part) */
+                    const double *m = &di->acc[((u * d->npts + p) * d->nf + f) * 2];
+                    v[u][0] -= m[1];
+                    v[u][1] += m[0];
+                }
+            }
             /* (E x H*)_a = E_t1 H_t2* - E_t2 H_t1*; real part of u v* = ur vr + ui vi */
-            s += (e1[0] * h2[0] + e1[1] * h2[1]) - (e2[0] * h1[0] + e2[1] * h1[1]);
+            s += (v[0][0] * v[3][0] + v[0][1] * v[3][1]) - (v[1][0] * v[2][0] + v[1][1] * v[2][1]);
         }
         flux[f] = s;
     }
