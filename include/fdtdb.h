@@ -194,6 +194,28 @@ fdtdb_status fdtdb_add_dft_flux(fdtdb_grid g, int axis, const fdtdb_box *plane, 
  * with rho = 1/(sigma omega0^2) (Drude: 1/omega_p^2).  FP64 sums. */
 fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int every, int *monitor_id);
 
+/* Bloch-periodic grids (the boundary condition along y of the paper's 2D runs, Appendix "Simulation
+ * details", here with any phase): couple two grids, re and im, as the real and imaginary parts of one
+ * grid of complex fields with f(r + n_a e_a) = exp(i phase[a]) f(r) on each axis a (phase[a] = k_a n_a
+ * in radians; 0 on a periodic axis keeps it plain periodic; phase[a] != 0 needs a periodic axis).
+ * Every update has real coefficients, so each part advances by the ordinary step except where a
+ * neighbour read crosses a Bloch axis: there it reads part p of exp(+-i phase[a]) (own + i other).
+ * Both grids must have the same dimension, shape, boundaries, dtype, Courant number and stream (an im
+ * created with a NULL stream gives up its own and takes re's; the stream goes with whichever part is
+ * destroyed last), the
+ * same set-up of materials and monitors, and no learned closure; sources are per part (the sources
+ * of im carry the imaginary part of a complex source profile).  Call after the set-up, before the
+ * first step.  Afterwards: fdtdb_step(re, n) advances both parts (E of both, then H of both, every
+ * step; direct launches, graph mode unused) and fdtdb_step(im, n) returns E_STATE; fdtdb_dft_flux(re)
+ * returns the flux of the complex fields Re sum (E~ x conj H~) with E~ = E~_re + i E~_im (its raw
+ * output: re's accumulators), fdtdb_dft_flux(im, id, NULL, raw) only im's accumulators; energies,
+ * fields and material state are read per part (the conserved energy is the sum over both parts,
+ * so the energy-growth watchdog is off on pairs).  Bloch grids run the generic per-cell kernels.
+ * Destroying one part leaves the other unable to step (E_STATE).  Errors: E_INVALID for mismatched
+ * grids, a phase on a non-periodic axis or a flux plane normal to a Bloch axis at its first cell;
+ * E_STATE when either grid has stepped, is already paired or holds a learned closure. */
+fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double phase[3]);
+
 /* -------------------------------------------------------------------------------------- stepping */
 
 /* Enqueue nsteps full time steps on the grid's stream and return without
@@ -234,8 +256,9 @@ fdtdb_status fdtdb_load_state(fdtdb_grid g, const char *path);
 /* ------------------------------------------------------------------------------------- read-out */
 /* All read-outs synchronize the grid's stream first. */
 
-/* flux: nfreq doubles.  raw (nullable): [4][npts][nfreq][2] doubles, the
- * complex accumulators of E_t1, E_t2, H_t1, H_t2 (t1, t2 cyclic after axis). */
+/* flux: nfreq doubles (nullable when raw is given).  raw (nullable): [4][npts][nfreq][2] doubles,
+ * the complex accumulators of E_t1, E_t2, H_t1, H_t2 (t1, t2 cyclic after axis).  Bloch pairs: see
+ * fdtdb_pair_bloch. */
 fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int monitor_id, double *flux, double *raw);
 
 /* out: capacity x 3 doubles [field, pol, bath]; *n_samples receives the number recorded. */

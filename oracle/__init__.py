@@ -241,10 +241,13 @@ class Oracle:
         """Polarization of one term of a multi-term material."""
         m = self.p.materials[mi]
         nc = int(np.prod([m.box[1][a] - m.box[0][a] for a in range(3)]))
-        out = np.zeros(nc, np.float64)
-        if lib().or_get_P_pole(self.g, mi, comp, level, pole, out) != 0:
-            raise ValueError("no such term")
-        return out
+
+        def one(g):
+            out = np.zeros(nc, np.float64)
+            if lib().or_get_P_pole(g, mi, comp, level, pole, out) != 0:
+                raise ValueError("no such term")
+            return out
+        return self._both(one)
 
     def set_pole(self, mi: int, comp: int, pole: int, level: int, values: np.ndarray):
         if lib().or_set_P_pole(self.g, mi, comp, level, pole, np.ascontiguousarray(values, np.float64).ravel()) != 0:

@@ -179,6 +179,12 @@ struct EArgs {
     long long block_base;            // first partial slot of this launch
     const RegionTable *rd;           // grouped launch: region table (nrd > 0), else the box above
     int nrd;
+    // Bloch pair (generic kernel only): H of the other part; a read of H across the lower end of
+    // periodic axis a returns bcos[a] own - bsin[a] other (bsin = -sin phi_a on the real part,
+    // +sin phi_a on the imaginary part); bloch = 0: a real grid, Htw unused
+    int bloch;
+    const void *Htw[3];
+    double bcos[3], bsin[3];
 };
 
 struct HArgs {
@@ -193,6 +199,10 @@ struct HArgs {
     const double *pml_b[3], *pml_c[3];
     const RegionTable *rd;           // grouped launch: region table (nrd > 0)
     int nrd;
+    // Bloch pair: E of the other part; a read of E across the upper end of periodic axis a returns
+    // bcos[a] own + bsin[a] other (sign convention of EArgs)
+    const void *Etw[3];
+    double bcos[3], bsin[3];
 };
 
 struct DftArgs {

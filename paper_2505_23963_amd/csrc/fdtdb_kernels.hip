@@ -93,6 +93,26 @@ __device__ __forceinline__ double at_plus(const void *f, int q, int coord, int s
     return ok ? v : 0.0;
 }
 
+// Bloch-periodic axes (the fields are complex, f(r + n_a e_a) = exp(i phi_a) f(r), held as two real
+// grids): a neighbour read that wraps past the lower end returns part p of exp(-i phi_a) (v + i w) and
+// one past the upper end part p of exp(+i phi_a) (v + i w), with v this part's value and w the other
+// part's; with bs = -sin phi_a on the real part and +sin phi_a on the imaginary part these are
+// bc v - bs w and bc v + bs w.  tw == nullptr (a real grid): the plain reads.
+template <typename T>
+__device__ __forceinline__ double at_minus_bloch(const void *f, const void *tw, int q, int coord, int stride, int n,
+                                                 int per, double bc, double bs) {
+    const double v = at_minus<T>(f, q, coord, stride, n, per);
+    if (tw == nullptr || coord > 0 || !per) return v;
+    return bc * v - bs * (double)static_cast<const T *>(tw)[q + (n - 1) * stride];
+}
+template <typename T>
+__device__ __forceinline__ double at_plus_bloch(const void *f, const void *tw, int q, int coord, int stride, int n,
+                                                int per, double bc, double bs) {
+    const double v = at_plus<T>(f, q, coord, stride, n, per);
+    if (tw == nullptr || coord < n - 1 || !per) return v;
+    return bc * v + bs * (double)static_cast<const T *>(tw)[q - (n - 1) * stride];
+}
+
 typedef const __attribute__((address_space(4))) float *cfptr;
 
 // soft-current term dt J(t_n) profile / eps of component c at cell (i, j, k)
@@ -417,9 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
             const int a1 = curl_a1(c), a2 = curl_a2(c);
             double t1 = 0.0, t2 = 0.0;
             if (axis_live(DIM, a1) && h_active(DIM, a2))
-                t1 = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+                t1 = ldd<T>(a.H[a2], q) - at_minus_bloch<T>(a.H[a2], a.Htw[a2], q, coord[a1], stride[a1], a.n[a1],
+                                                             a.per[a1], a.bcos[a1], a.bsin[a1]);
             if (axis_live(DIM, a2) && h_active(DIM, a1))
-                t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+                t2 = ldd<T>(a.H[a1], q) - at_minus_bloch<T>(a.H[a1], a.Htw[a1], q, coord[a2], stride[a2], a.n[a2],
+                                                             a.per[a2], a.bcos[a2], a.bsin[a2]);
             if (PML) {
                 if (R.psi[c][0]) {
                     T *ps = static_cast<T *>(R.psi[c][0]);
@@ -799,9 +821,11 @@ __global__ __launch_bounds__(kBlock) void k_update_h(const HArgs a) {
         const int a1 = curl_a1(c), a2 = curl_a2(c);
         double t1 = 0.0, t2 = 0.0;
         if (axis_live(DIM, a1) && e_active(DIM, a2))
-            t1 = at_plus<T>(a.E[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]) - ldd<T>(a.E[a2], q);
+            t1 = at_plus_bloch<T>(a.E[a2], a.Etw[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1], a.bcos[a1],
+                                  a.bsin[a1]) - ldd<T>(a.E[a2], q);
         if (axis_live(DIM, a2) && e_active(DIM, a1))
-            t2 = at_plus<T>(a.E[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]) - ldd<T>(a.E[a1], q);
+            t2 = at_plus_bloch<T>(a.E[a1], a.Etw[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2], a.bcos[a2],
+                                  a.bsin[a2]) - ldd<T>(a.E[a1], q);
         if (PML) {
             if (R.psi[c][0]) {
                 T *ps = static_cast<T *>(R.psi[c][0]);
@@ -1383,14 +1407,28 @@ __global__ __launch_bounds__(kBlock) void k_dft_flush(const double *stage, const
     }
 }
 
-// flux[f] = Re sum_p (E1 conj(H2) - E2 conj(H1))
-__global__ __launch_bounds__(kBlock) void k_dft_flux(const double2 *acc, int npts, int nf, double *flux) {
+// flux[f] = Re sum_p (E1 conj(H2) - E2 conj(H1)).  Bloch pair (acc_im != nullptr): the transforms are
+// those of the complex fields, acc + i acc_im (acc, acc_im: the real and imaginary parts' transforms).
+__device__ __forceinline__ double2 dft_value(const double2 *acc, const double2 *acc_im, long long i) {
+    double2 v = acc[i];
+    if (acc_im) {
+        const double2 w = acc_im[i];
+        v.x -= w.y;
+        v.y += w.x;
+    }
+    return v;
+}
+__global__ __launch_bounds__(kBlock) void k_dft_flux(const double2 *acc, const double2 *acc_im, int npts, int nf,
+                                                     double *flux) {
     const int f = blockIdx.x;
-    const double2 *e1 = acc + (0LL * nf + f) * npts, *e2 = acc + (1LL * nf + f) * npts;
-    const double2 *h1 = acc + (2LL * nf + f) * npts, *h2 = acc + (3LL * nf + f) * npts;
+    const long long o1 = (0LL * nf + f) * npts, o2 = (1LL * nf + f) * npts;
+    const long long o3 = (2LL * nf + f) * npts, o4 = (3LL * nf + f) * npts;
     double s = 0.0, z1 = 0.0, z2 = 0.0;
-    for (int p = threadIdx.x; p < npts; p += kBlock)
-        s += (e1[p].x * h2[p].x + e1[p].y * h2[p].y) - (e2[p].x * h1[p].x + e2[p].y * h1[p].y);
+    for (int p = threadIdx.x; p < npts; p += kBlock) {
+        const double2 e1 = dft_value(acc, acc_im, o1 + p), e2 = dft_value(acc, acc_im, o2 + p);
+        const double2 h1 = dft_value(acc, acc_im, o3 + p), h2 = dft_value(acc, acc_im, o4 + p);
+        s += (e1.x * h2.x + e1.y * h2.y) - (e2.x * h1.x + e2.y * h1.y);
+    }
     block_sum3(s, z1, z2);
     if (threadIdx.x == 0) flux[f] = s;
 }
@@ -1431,20 +1469,23 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
     constexpr int NC = DIM == 3 ? 3 : 1;
+    // the specialised bath kernels read no other part: real grids only (a Bloch pair takes k_update_e)
     if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16) {
-        BathCoef<NG> cf;
-        for (int h = 0; h < 3; ++h) cf.head[h] = coef_host[h];
-        for (int j = 0; j < 4 * NG; ++j)
-            for (int u = 0; u < 5; ++u) cf.md[j][u] = coef_host[kCoefHead + j * kCoefMode + u];
-        if (energy)
-            hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
-        else if constexpr (DIM == 3 && NC * NG > 6)
-            hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
-                               dim3(kBathBlock), kBathLdsReserve, s, a, cf);
-        else
-            hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>), dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)),
-                               dim3(kBlock), 0, s, a, cf);
-        return hipGetLastError();
+        if (!a.bloch) {
+            BathCoef<NG> cf;
+            for (int h = 0; h < 3; ++h) cf.head[h] = coef_host[h];
+            for (int j = 0; j < 4 * NG; ++j)
+                for (int u = 0; u < 5; ++u) cf.md[j][u] = coef_host[kCoefHead + j * kCoefMode + u];
+            if (energy)
+                hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
+            else if constexpr (DIM == 3 && NC * NG > 6)
+                hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
+                                   dim3(kBathBlock), kBathLdsReserve, s, a, cf);
+            else
+                hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>),
+                                   dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)), dim3(kBlock), 0, s, a, cf);
+            return hipGetLastError();
+        }
     }
     if (energy)
         hipLaunchKernelGGL((k_update_e<DIM, T, KIND, NG, PML, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
@@ -1582,8 +1623,8 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
     return hipGetLastError();
 }
 
-hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s) {
-    hipLaunchKernelGGL(k_dft_flux, dim3(nf), dim3(kBlock), 0, s, acc, npts, nf, flux);
+hipError_t launch_dft_flux(const double2 *acc, const double2 *acc_im, int npts, int nf, double *flux, hipStream_t s) {
+    hipLaunchKernelGGL(k_dft_flux, dim3(nf), dim3(kBlock), 0, s, acc, acc_im, npts, nf, flux);
     return hipGetLastError();
 }
 

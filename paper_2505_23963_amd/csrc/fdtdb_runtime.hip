@@ -27,7 +27,7 @@ hipError_t launch_energy_reduce(const Clock *clk, const double *partial, long lo
 hipError_t launch_dft_stage(bool f64, const DftArgs &a, hipStream_t s);
 hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int nslots, double dt, double *tw,
                             const double *stage, int npts, double2 *acc, hipStream_t s);
-hipError_t launch_dft_flux(const double2 *acc, int npts, int nf, double *flux, hipStream_t s);
+hipError_t launch_dft_flux(const double2 *acc, const double2 *acc_im, int npts, int nf, double *flux, hipStream_t s);
 hipError_t launch_nonfinite(bool f64, const void *f, long long n, int *flag, hipStream_t s);
 hipError_t launch_to_f64(bool f64, const void *src, long long n, double *dst, hipStream_t s);
 hipError_t launch_probe(bool f64, const void *E, const void *P, const int *q, const int *m, int n, const Clock *clk,
@@ -190,6 +190,12 @@ struct fdtdb_grid_s {
     int *flag_dev = nullptr;
     bool finalized = false;
     long long steps = 0;          // steps enqueued
+    // Bloch pair: the grid of the other part, this grid's part (0 real, 1 imaginary), the phase of each
+    // axis; orphan: the other part was destroyed (this grid can no longer step)
+    fdtdb_grid_s *twin = nullptr;
+    int part = 0;
+    double bph[3] = {0.0, 0.0, 0.0};
+    bool orphan = false;
     long long total_blocks = 0;   // E-kernel blocks over all regions (energy partial slots)
     // graphs
     int graph_chunk = 0;
@@ -318,7 +324,7 @@ double pml_sigma(const fdtdb_grid_s *g, int a, double pos) {
 // shared by two regions is fetched and partially written by both); psi is again zero on the
 // extra nodes.
 bool z_tail_h(const fdtdb_grid_s *g) {
-    return g->ndim == 3 && g->bc[2] == FDTDB_BC_PML && g->n[2] % 4 == 0 && g->pml[2] % 4 == 0;
+    return g->ndim == 3 && g->bc[2] == FDTDB_BC_PML && g->n[2] % 4 == 0 && g->pml[2] % 4 == 0 && !g->twin;
 }
 
 int upper_pml_cut(const fdtdb_grid_s *g, int a, bool h) {
@@ -570,8 +576,8 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
             if (rg.mat >= 0) {
                 const Material &mt = g->mats[rg.mat];
                 const bool m4 = mt.mext[2] % 4 == 0 && (rg.lo[2] - (int)mt.lo[2]) % 4 == 0;
-                (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy ? drude4 : solo).push_back(i);
-            } else if ((z4(rg) || bg_unaligned4(rg)) && !rg.energy) {
+                (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy && !g->twin ? drude4 : solo).push_back(i);
+            } else if ((z4(rg) || bg_unaligned4(rg)) && !rg.energy && !g->twin) {   // Bloch pairs: generic kernels
                 bg4.push_back(i);
             } else {
                 bg.push_back(i);
@@ -585,7 +591,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         for (int i = 0; i < (int)g->hregions.size(); i++) {
             if (g->hregions[i].zw && !z4(g->hregions[i]))   // per-row psi slots: vector kernel only
                 return fail(FDTDB_E_STATE, "H region with per-row psi slots but no 4-aligned z range");
-            (z4(g->hregions[i]) ? h4 : hg).push_back(i);
+            (z4(g->hregions[i]) && !g->twin ? h4 : hg).push_back(i);
         }
         make(g->hlaunch, g->hregions, h4, true, true);
         make(g->hlaunch, g->hregions, hg, hg.size() > 1, false);
@@ -718,7 +724,16 @@ fdtdb_status collect_events(fdtdb_grid_s *g) {
 }
 
 // enqueue one full step (no host synchronization)
-fdtdb_status enqueue_step(fdtdb_grid_s *g) {
+// cos phi_a and (part 0: -sin phi_a, part 1: +sin phi_a) of every axis of a Bloch pair
+void bloch_coefs(const fdtdb_grid_s *g, double *bc, double *bs) {
+    for (int ax = 0; ax < 3; ax++) {
+        bc[ax] = std::cos(g->bph[ax]);
+        bs[ax] = (g->part == 0 ? -1.0 : 1.0) * std::sin(g->bph[ax]);
+    }
+}
+
+// the E half of a step: clock, E and material launches, energy sums, probes
+fdtdb_status enqueue_e(fdtdb_grid_s *g) {
     const long long n = g->steps;
     const int cur = (int)(n & 1), nxt = cur ^ 1;
     HIP_TRY(launch_tick(g->clock, g->src_dev, (int)g->srcs.size(), g->dt, g->stream));
@@ -726,6 +741,11 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
         const Region &r = g->regions[L.regs[0]];
         EArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
+        if (g->twin) {
+            a.bloch = 1;
+            for (int c = 0; c < 3; c++) a.Htw[c] = g->twin->H[c];
+            bloch_coefs(g, a.bcos, a.bsin);
+        }
         fill_fields(g, a.n, a.per);
         for (int ax = 0; ax < 3; ax++) { a.lo[ax] = r.lo[ax]; a.ext[ax] = r.hi[ax] - r.lo[ax]; }
         a.ext12 = a.ext[1] * a.ext[2];
@@ -812,10 +832,19 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     for (auto &pr : g->probes)
         HIP_TRY(launch_probe(g->f64, g->E[pr.comp], g->mats[pr.mat].P[nxt][pr.comp], pr.q, pr.m, pr.n, g->clock,
                              pr.capacity, pr.E, pr.P, g->stream));
+    return FDTDB_OK;
+}
+
+// the H half of a step
+fdtdb_status enqueue_h(fdtdb_grid_s *g) {
     for (auto &L : g->hlaunch) {
         const Region &r = g->hregions[L.regs[0]];
         HArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
+        if (g->twin) {
+            for (int c = 0; c < 3; c++) a.Etw[c] = g->twin->E[c];
+            bloch_coefs(g, a.bcos, a.bsin);
+        }
         fill_fields(g, a.n, a.per);
         for (int ax = 0; ax < 3; ax++) { a.lo[ax] = r.lo[ax]; a.ext[ax] = r.hi[ax] - r.lo[ax]; }
         a.ext12 = a.ext[1] * a.ext[2];
@@ -844,6 +873,11 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
             g->pending.push_back(pe);
         }
     }
+    return FDTDB_OK;
+}
+
+// the monitors' DFT staging of a step, and the step count
+fdtdb_status enqueue_dft(fdtdb_grid_s *g) {
     for (auto &d : g->dfts) {
         DftArgs a{};
         a.axis = d.axis;
@@ -861,6 +895,24 @@ fdtdb_status enqueue_step(fdtdb_grid_s *g) {
     }
     g->steps++;
     return FDTDB_OK;
+}
+
+fdtdb_status enqueue_step(fdtdb_grid_s *g) {
+    TRY(enqueue_e(g));
+    TRY(enqueue_h(g));
+    return enqueue_dft(g);
+}
+
+// one step of a Bloch pair (both parts on one stream): each half step runs on both parts before the next
+// half step, so that the reads across a Bloch axis see the other part at the same time level
+fdtdb_status enqueue_pair_step(fdtdb_grid_s *re) {
+    fdtdb_grid_s *im = re->twin;
+    TRY(enqueue_e(re));
+    TRY(enqueue_e(im));
+    TRY(enqueue_h(re));
+    TRY(enqueue_h(im));
+    TRY(enqueue_dft(re));
+    return enqueue_dft(im);
 }
 
 fdtdb_status sync(fdtdb_grid_s *g) {
@@ -953,6 +1005,7 @@ uint64_t fingerprint(const fdtdb_grid_s *g) {
     Fnv f;
     f.v(g->ndim); f.bytes(g->n, sizeof g->n); f.v(g->dt); f.v(g->R0); f.v(g->f64);
     f.bytes(g->bc, sizeof g->bc); f.bytes(g->pml, sizeof g->pml);
+    f.v(g->twin != nullptr); f.v(g->part); f.bytes(g->bph, sizeof g->bph);
     f.v(g->mats.size());
     for (auto &m : g->mats) {
         f.v(m.kind); f.bytes(m.lo, sizeof m.lo); f.bytes(m.hi, sizeof m.hi); f.v(m.eps); f.v(m.omega0);
@@ -1086,6 +1139,14 @@ fdtdb_status fdtdb_create_grid(const fdtdb_grid_desc *d, fdtdb_grid *out) {
 
 fdtdb_status fdtdb_destroy_grid(fdtdb_grid g) {
     if (!g) return FDTDB_OK;
+    if (g->twin) {
+        if (g->own_stream && g->twin->stream == g->stream) {   // the other part keeps the shared stream
+            g->twin->own_stream = true;
+            g->own_stream = false;
+        }
+        g->twin->twin = nullptr;
+        g->twin->orphan = true;
+    }
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     if (g->graph) (void)hipGraphExecDestroy(g->graph);
     for (auto &p : g->pending) { g->pool.push_back(p.a); g->pool.push_back(p.b); }
@@ -1279,6 +1340,7 @@ fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *
                                     const double *scales) {
     if (!g || !weights || !scales) return fail(FDTDB_E_INVALID, "null argument");
     if (g->finalized) return fail(FDTDB_E_STATE, "closures must be set before the first step");
+    if (g->twin || g->orphan) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
     if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH)
         return fail(FDTDB_E_INVALID, "the closure replaces the bath of a Lorentz-Bath material");
     if (width != kClosureWidth) return fail(FDTDB_E_INVALID, "closure width must be %d", kClosureWidth);
@@ -1383,6 +1445,8 @@ fdtdb_status fdtdb_add_dft_flux(fdtdb_grid g, int axis, const fdtdb_box *plane, 
     if (axis < 0 || axis >= g->ndim) return fail(FDTDB_E_INVALID, "bad axis");
     if (!box_ok(g, plane) || plane->hi[axis] != plane->lo[axis] + 1)
         return fail(FDTDB_E_INVALID, "flux plane must be inside the grid and one cell thick along its axis");
+    if (g->twin && g->bph[axis] != 0.0 && plane->lo[axis] == 0)
+        return fail(FDTDB_E_INVALID, "a flux plane normal to a Bloch axis cannot sit at its first cell");
     if (nfreq < 1 || !omega) return fail(FDTDB_E_INVALID, "need frequencies");
     Dft d;
     d.axis = axis;
@@ -1483,6 +1547,22 @@ fdtdb_status fdtdb_set_graph(fdtdb_grid g, int chunk_steps) {
 fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps) {
     if (!g) return fail(FDTDB_E_INVALID, "null grid");
     if (nsteps < 0) return fail(FDTDB_E_INVALID, "nsteps < 0");
+    if (g->orphan) return fail(FDTDB_E_STATE, "the other part of this Bloch grid was destroyed");
+    if (g->twin) {
+        if (g->part != 0) return fail(FDTDB_E_STATE, "a Bloch pair steps through its real part");
+        fdtdb_grid_s *im = g->twin;
+        if (g->dfts.size() != im->dfts.size()) return fail(FDTDB_E_STATE, "the parts need the same flux monitors");
+        for (size_t i = 0; i < g->dfts.size(); i++)
+            if (g->dfts[i].npts != im->dfts[i].npts || g->dfts[i].nf != im->dfts[i].nf)
+                return fail(FDTDB_E_STATE, "the parts need the same flux monitors");
+        TRY(finalize(g));
+        TRY(finalize(im));
+        if (g->steps != im->steps) return fail(FDTDB_E_STATE, "the two parts of the Bloch pair are at different steps");
+        TRY(ensure_energy_capacity(g, g->steps + nsteps));
+        TRY(ensure_energy_capacity(im, im->steps + nsteps));
+        for (int64_t s = 0; s < nsteps; s++) TRY(enqueue_pair_step(g));
+        return FDTDB_OK;
+    }
     TRY(finalize(g));
     TRY(ensure_energy_capacity(g, g->steps + nsteps));
     int64_t left = nsteps;
@@ -1515,6 +1595,47 @@ fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps) {
     return FDTDB_OK;
 }
 
+fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double *phase) {
+    if (!re || !im || !phase || re == im) return fail(FDTDB_E_INVALID, "need two grids and the phases");
+    if (re->finalized || im->finalized) return fail(FDTDB_E_STATE, "grids are paired before their first step");
+    if (re->twin || im->twin || re->orphan || im->orphan) return fail(FDTDB_E_STATE, "grid already paired");
+    if (re->ndim != im->ndim || re->f64 != im->f64 || re->dt != im->dt || re->R0 != im->R0)
+        return fail(FDTDB_E_INVALID, "the parts need the same dimension, precision and time step");
+    // one stream for both parts: an imaginary part that created its own stream takes the real part's
+    if (re->stream != im->stream && !im->own_stream)
+        return fail(FDTDB_E_INVALID, "the parts need the same stream");
+    for (int a = 0; a < 3; a++) {
+        if (re->n[a] != im->n[a] || re->bc[a] != im->bc[a] || re->pml[a] != im->pml[a])
+            return fail(FDTDB_E_INVALID, "the parts need the same shape and boundaries");
+        if (!std::isfinite(phase[a])) return fail(FDTDB_E_INVALID, "non-finite phase");
+        if (phase[a] != 0.0 && (a >= re->ndim || re->bc[a] != FDTDB_BC_PERIODIC))
+            return fail(FDTDB_E_INVALID, "a Bloch phase needs a periodic axis of the grid");
+    }
+    for (const fdtdb_grid_s *g : {re, im})
+        for (auto &m : g->mats)
+            if (m.cw_dev) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
+    if (re->dfts.size() != im->dfts.size()) return fail(FDTDB_E_INVALID, "the parts need the same flux monitors");
+    for (size_t i = 0; i < re->dfts.size(); i++) {
+        const Dft &a = re->dfts[i], &b = im->dfts[i];
+        if (a.axis != b.axis || a.npts != b.npts || a.nf != b.nf)
+            return fail(FDTDB_E_INVALID, "the parts need the same flux monitors");
+        if (phase[a.axis] != 0.0 && a.lo[a.axis] == 0)
+            return fail(FDTDB_E_INVALID, "a flux plane normal to a Bloch axis cannot sit at its first cell");
+    }
+    if (re->stream != im->stream) {
+        HIP_TRY(hipStreamSynchronize(im->stream));
+        HIP_TRY(hipStreamDestroy(im->stream));
+        im->stream = re->stream;
+        im->own_stream = false;
+    }
+    re->twin = im;
+    im->twin = re;
+    re->part = 0;
+    im->part = 1;
+    for (int a = 0; a < 3; a++) re->bph[a] = im->bph[a] = phase[a];
+    return FDTDB_OK;
+}
+
 fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps) {
     if (!g || !steps) return fail(FDTDB_E_INVALID, "null argument");
     *steps = g->steps;
@@ -1528,6 +1649,7 @@ fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps) {
 // then, while above 1 % of its value when the sources ended, marks an instability long before any
 // field overflows.
 fdtdb_status energy_watchdog(fdtdb_grid_s *g) {
+    if (g->twin || g->orphan) return FDTDB_OK;   // a Bloch pair conserves the sum over both parts only
     double t_off = 0.0;
     for (auto &x : g->srcs) t_off = std::max(t_off, 10.0 / x.width);
     for (auto &e : g->ens) {
@@ -1576,12 +1698,21 @@ fdtdb_status fdtdb_synchronize(fdtdb_grid g) {
 }
 
 fdtdb_status fdtdb_dft_flux(fdtdb_grid g, int id, double *flux, double *raw) {
-    if (!g || id < 0 || id >= (int)g->dfts.size() || !flux) return fail(FDTDB_E_INVALID, "bad monitor");
+    if (!g || id < 0 || id >= (int)g->dfts.size() || (!flux && !raw)) return fail(FDTDB_E_INVALID, "bad monitor");
+    if (flux && g->twin && g->part != 0) return fail(FDTDB_E_STATE, "the flux of a Bloch pair is read from its real part");
+    if (flux && !g->twin && g->orphan) return fail(FDTDB_E_STATE, "the other part of this Bloch grid was destroyed");
     Dft &d = g->dfts[id];
+    if (flux && g->twin && id >= (int)g->twin->dfts.size()) return fail(FDTDB_E_STATE, "monitor missing on the other part");
+    Dft *di = g->twin && flux ? &g->twin->dfts[id] : nullptr;
     if (g->finalized) TRY(flush_dft(g, d));
-    if (g->finalized) HIP_TRY(launch_dft_flux(d.acc, d.npts, d.nf, d.flux_dev, g->stream));
-    TRY(sync(g));
-    HIP_TRY(hipMemcpy(flux, d.flux_dev, 8 * (size_t)d.nf, hipMemcpyDeviceToHost));
+    if (di && g->twin->finalized) TRY(flush_dft(g->twin, *di));
+    if (flux) {
+        if (g->finalized) HIP_TRY(launch_dft_flux(d.acc, di ? di->acc : nullptr, d.npts, d.nf, d.flux_dev, g->stream));
+        TRY(sync(g));
+        HIP_TRY(hipMemcpy(flux, d.flux_dev, 8 * (size_t)d.nf, hipMemcpyDeviceToHost));
+    } else {
+        TRY(sync(g));
+    }
     if (raw) {
         // device layout [field][f][p] -> ABI layout [field][p][f]
         std::vector<double2> tmp((size_t)4 * d.nf * d.npts);

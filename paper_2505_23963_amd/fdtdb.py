@@ -71,6 +71,7 @@ SIGNATURES = [
     ("fdtdb_add_dft_flux", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_int, _dp, C.POINTER(C.c_int)]),
     ("fdtdb_add_energy_monitor", C.c_int, [C.c_void_p, C.POINTER(Box), C.c_int, C.POINTER(C.c_int)]),
     ("fdtdb_step", C.c_int, [C.c_void_p, C.c_int64]),
+    ("fdtdb_pair_bloch", C.c_int, [C.c_void_p, C.c_void_p, _dp]),
     ("fdtdb_synchronize", C.c_int, [C.c_void_p]),
     ("fdtdb_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("fdtdb_set_graph", C.c_int, [C.c_void_p, C.c_int]),
@@ -222,13 +223,41 @@ def bath_params(form: str, omega0: float, gamma0: float, n_bath: int, width: flo
 
 
 class Grid:
-    """A device grid built from an fdtdb_inputs Problem description."""
+    """A device grid built from an fdtdb_inputs Problem description.  A problem with Bloch phases
+    (problem.bloch) becomes two device grids coupled by fdtdb_pair_bloch, the real (h) and imaginary
+    (h_im) parts of complex fields: fields, material state and the flux's raw transforms then read
+    back complex, energies as the sum over both parts."""
 
     def __init__(self, problem, stream: Optional[int] = None, graph_chunk: int = 0, dtype: Optional[str] = None,
                  closures: Optional[dict] = None):
         """closures: {material index: {"weights": 1477 floats, "scales": (s_E, s_P, s_V, s_S)}}."""
-        L = lib()
         self.p = problem
+        self._probes = {}
+        self.h_im = None
+        self.h, self.mat_ids = self._build(problem, stream, dtype, closures, 0)
+        if problem.bloch is not None:
+            if closures:
+                raise ValueError("learned closures are not available on Bloch grids")
+            self.h_im, _ = self._build(problem, stream, dtype, None, 1)
+            ph = _arr(problem.bloch)
+            _check(lib().fdtdb_pair_bloch(self.h, self.h_im, _ptr(ph)))
+        elif graph_chunk:
+            _check(lib().fdtdb_set_graph(self.h, int(graph_chunk)))
+
+    @property
+    def _parts(self):
+        return [self.h] if self.h_im is None else [self.h, self.h_im]
+
+    def _both(self, fn):
+        """fn(handle) of the real part, + 1j fn(handle) of the imaginary part of a Bloch grid"""
+        v = fn(self.h)
+        return v if self.h_im is None else v + 1j * fn(self.h_im)
+
+    @staticmethod
+    def _build(problem, stream, dtype, closures, part):
+        """One device grid with the problem's set-up; part 1 (imaginary part of a Bloch grid) takes the
+        imaginary parts of the source profiles (sources without one drive the real part only)."""
+        L = lib()
         d = GridDesc()
         d.ndim = problem.ndim
         for a in range(3):
@@ -241,18 +270,16 @@ class Grid:
         d.pml_R0 = problem.pml_R0
         d.hip_stream = stream
         h = C.c_void_p()
-        self._probes = {}
         _check(L.fdtdb_create_grid(C.byref(d), C.byref(h)))
-        self.h = h
-        self.mat_ids = []
+        mat_ids = []
         for m in problem.materials:
             kind = type(m).__name__
             mid = C.c_int(-1)
             b = _box(m.box)
             if kind == "Dielectric":
-                _check(L.fdtdb_set_eps_inf(self.h, C.byref(b), m.eps_inf, C.byref(mid)))
+                _check(L.fdtdb_set_eps_inf(h, C.byref(b), m.eps_inf, C.byref(mid)))
             elif kind == "Drude":
-                _check(L.fdtdb_set_drude(self.h, C.byref(b), m.omega_p, m.gamma, m.eps_inf, C.byref(mid)))
+                _check(L.fdtdb_set_drude(h, C.byref(b), m.omega_p, m.gamma, m.eps_inf, C.byref(mid)))
             elif kind == "LorentzBath":
                 if m.n_bath and m.form is not None:
                     wj, gj, kj = bath_params(m.form, m.omega0, m.gamma0, m.n_bath, m.width, m.bath_gamma,
@@ -260,38 +287,41 @@ class Grid:
                 else:
                     wj, gj, kj = _arr(m.omega_j), _arr(m.gamma_j), _arr(m.k_j)
                 sig = _arr(m.sigma_cells)
-                _check(L.fdtdb_set_lorentz_bath(self.h, C.byref(b), m.omega0, m.gamma0, m.eps_inf, _ptr(sig),
+                _check(L.fdtdb_set_lorentz_bath(h, C.byref(b), m.omega0, m.gamma0, m.eps_inf, _ptr(sig),
                                                 m.sigma, m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj), C.byref(mid)))
             elif kind == "MultiPole":
                 nt = len(m.kinds)
                 kinds = (C.c_int * nt)(*[{"lorentz": 0, "drude": 1}[k] for k in m.kinds])
                 om, ga, sg = (np.ascontiguousarray(v, np.float64) for v in (m.omega, m.gamma, m.sigma))
-                _check(L.fdtdb_set_multi_term(self.h, C.byref(b), m.eps_inf, nt, kinds, _ptr(om), _ptr(ga), _ptr(sg),
+                _check(L.fdtdb_set_multi_term(h, C.byref(b), m.eps_inf, nt, kinds, _ptr(om), _ptr(ga), _ptr(sg),
                                               C.byref(mid)))
             else:
                 raise TypeError(kind)
-            self.mat_ids.append(mid.value)
+            mat_ids.append(mid.value)
         for mi, cl in (closures or {}).items():
             w = np.ascontiguousarray(cl["weights"], dtype=np.float32).ravel()
             sc = _arr(cl["scales"])
-            _check(L.fdtdb_set_bath_closure(self.h, self.mat_ids[mi], w.ctypes.data_as(C.POINTER(C.c_float)), 32,
+            _check(L.fdtdb_set_bath_closure(h, mat_ids[mi], w.ctypes.data_as(C.POINTER(C.c_float)), 32,
                                             _ptr(sc)))
         for s in problem.sources:
-            prof = _arr(s.profile)
-            _check(L.fdtdb_add_source(self.h, s.comp, C.byref(_box(s.box)), s.omega_c, s.width, s.amplitude,
+            pr = s.profile if part == 0 else s.profile_im
+            if part == 1 and pr is None:
+                continue
+            prof = _arr(pr)
+            _check(L.fdtdb_add_source(h, s.comp, C.byref(_box(s.box)), s.omega_c, s.width, s.amplitude,
                                       _ptr(prof), None))
         for dm in problem.dfts:
             om = _arr(dm.omega)
-            _check(L.fdtdb_add_dft_flux(self.h, dm.axis, C.byref(_box(dm.box)), len(om), _ptr(om), None))
+            _check(L.fdtdb_add_dft_flux(h, dm.axis, C.byref(_box(dm.box)), len(om), _ptr(om), None))
         for e in problem.energies:
-            _check(L.fdtdb_add_energy_monitor(self.h, C.byref(_box(e.box)), e.every, None))
-        if graph_chunk:
-            _check(L.fdtdb_set_graph(self.h, int(graph_chunk)))
+            _check(L.fdtdb_add_energy_monitor(h, C.byref(_box(e.box)), e.every, None))
+        return h, mat_ids
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().fdtdb_destroy_grid(self.h)
-            self.h = None
+        for name in ("h_im", "h"):
+            if getattr(self, name, None):
+                lib().fdtdb_destroy_grid(getattr(self, name))
+                setattr(self, name, None)
 
     def __del__(self):
         try:
@@ -303,7 +333,8 @@ class Grid:
         _check(lib().fdtdb_step(self.h, int(n)))
 
     def synchronize(self):
-        _check(lib().fdtdb_synchronize(self.h))
+        for h in self._parts:
+            _check(lib().fdtdb_synchronize(h))
 
     @property
     def steps_done(self) -> int:
@@ -312,39 +343,50 @@ class Grid:
         return s.value
 
     def field(self, comp: int) -> np.ndarray:
-        out = np.zeros(self.p.cells, np.float64)
-        _check(lib().fdtdb_get_field(self.h, comp, out.ctypes.data_as(C.c_void_p), 0))
-        return out.reshape(self.p.n)
+        def one(h):
+            out = np.zeros(self.p.cells, np.float64)
+            _check(lib().fdtdb_get_field(h, comp, out.ctypes.data_as(C.c_void_p), 0))
+            return out.reshape(self.p.n)
+        return self._both(one)
 
-    def field_into(self, comp: int, device_ptr: int):
+    def field_into(self, comp: int, device_ptr: int, part: int = 0):
         """Write a field component (FP64, C order) into device memory at device_ptr (e.g. a torch
-        float64 CUDA tensor's data_ptr() of n[0]*n[1]*n[2] elements)."""
-        _check(lib().fdtdb_get_field(self.h, comp, C.c_void_p(device_ptr), 1))
+        float64 CUDA tensor's data_ptr() of n[0]*n[1]*n[2] elements); part 1: the imaginary part of a
+        Bloch grid."""
+        _check(lib().fdtdb_get_field(self._parts[part], comp, C.c_void_p(device_ptr), 1))
 
     def set_field(self, comp: int, values):
-        v = _arr(values)
-        _check(lib().fdtdb_set_field(self.h, comp, _ptr(v)))
+        _check(lib().fdtdb_set_field(self.h, comp, _ptr(_arr(np.real(values)))))
+        if self.h_im is not None:
+            _check(lib().fdtdb_set_field(self.h_im, comp, _ptr(_arr(np.imag(values)))))
 
     def _mcells(self, mi):
         b = self.p.materials[mi].box
         return int(np.prod([b[1][a] - b[0][a] for a in range(3)]))
 
     def polarization(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
-        out = np.zeros(self._mcells(mi), np.float64)
-        _check(lib().fdtdb_get_polarization(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
-        return out
+        def one(h):
+            out = np.zeros(self._mcells(mi), np.float64)
+            _check(lib().fdtdb_get_polarization(h, self.mat_ids[mi], comp, level, _ptr(out)))
+            return out
+        return self._both(one)
 
     def pole(self, mi: int, comp: int, term: int, level: int = 0) -> np.ndarray:
         """Polarization of one term of a multi-term material."""
-        out = np.zeros(self._mcells(mi), np.float64)
-        _check(lib().fdtdb_get_polarization_term(self.h, self.mat_ids[mi], comp, level, term, _ptr(out)))
-        return out
+        def one(h):
+            out = np.zeros(self._mcells(mi), np.float64)
+            _check(lib().fdtdb_get_polarization_term(h, self.mat_ids[mi], comp, level, term, _ptr(out)))
+            return out
+        return self._both(one)
 
     def bath(self, mi: int, comp: int, level: int = 0) -> np.ndarray:
         nb = self.p.materials[mi].n_bath
-        out = np.zeros(nb * self._mcells(mi), np.float64)
-        _check(lib().fdtdb_get_bath(self.h, self.mat_ids[mi], comp, level, _ptr(out)))
-        return out.reshape(nb, -1)
+
+        def one(h):
+            out = np.zeros(nb * self._mcells(mi), np.float64)
+            _check(lib().fdtdb_get_bath(h, self.mat_ids[mi], comp, level, _ptr(out)))
+            return out.reshape(nb, -1)
+        return self._both(one)
 
     def add_probe(self, mi: int, comp: int, cells, nsteps: int) -> int:
         """Record E^{n+1/2} and the new P at material-box cells for steps [0, nsteps)."""
@@ -377,15 +419,26 @@ class Grid:
         _check(lib().fdtdb_dft_flux(self.h, mid, _ptr(out), _ptr(r)))
         if raw:
             rr = r.reshape(4, npts, nf, 2)
-            return out, rr[..., 0] + 1j * rr[..., 1]
+            tr = rr[..., 0] + 1j * rr[..., 1]
+            if self.h_im is not None:    # transforms of the complex fields: real part's + 1j * imaginary part's
+                ri = np.zeros(4 * npts * nf * 2, np.float64)
+                _check(lib().fdtdb_dft_flux(self.h_im, mid, None, _ptr(ri)))
+                ri = ri.reshape(4, npts, nf, 2)
+                tr = tr + 1j * (ri[..., 0] + 1j * ri[..., 1])
+            return out, tr
         return out
 
     def energy(self, mid: int) -> np.ndarray:
-        n = C.c_int64()
-        _check(lib().fdtdb_energy(self.h, mid, None, 0, C.byref(n)))
-        out = np.zeros(3 * max(n.value, 1), np.float64)
-        _check(lib().fdtdb_energy(self.h, mid, _ptr(out), n.value, C.byref(n)))
-        return out[:3 * n.value].reshape(-1, 3)
+        """[field, polarization, bath] per sample (the sum over both parts of a Bloch grid)"""
+        tot = None
+        for h in self._parts:
+            n = C.c_int64()
+            _check(lib().fdtdb_energy(h, mid, None, 0, C.byref(n)))
+            out = np.zeros(3 * max(n.value, 1), np.float64)
+            _check(lib().fdtdb_energy(h, mid, _ptr(out), n.value, C.byref(n)))
+            e = out[:3 * n.value].reshape(-1, 3)
+            tot = e if tot is None else tot + e
+        return tot
 
     def save_state(self, path: str):
         """Write the whole time-stepping state to a file (fdtdb_save_state)."""

@@ -64,6 +64,36 @@ def test_loss_and_gradient_match_oracle_tbptt(act):
         off += n
 
 
+def test_adam_updates_match_oracle_adam_step():
+    """The GPU's Adam update (k_adam) element by element: two training epochs over a record of one window,
+    each against oracle/closure.adam_step applied to the GPU's own gradient at the same weights, so that the
+    comparison isolates the update (both moments, the bias corrections at t = 1 and t = 2, the FP64 master
+    weights and their FP32 copy): equal to one FP32 ulp."""
+    from paper_2505_23963_amd import closure_weights
+    N, T = 64, 64
+    E, P = configs.closure_record(N, T, seed=7)
+    d = _w32(configs.closure_init(23, hidden_scale=0.3, state_scale=0.05, force_scale=0.2))
+    tr = _trainer(N, T, T)
+    tr.load(E, P)
+    w = np.asarray(closure_weights(d), np.float32)
+    tr.set_weights(w)
+    p = {"w": w.astype(np.float64)}
+    m, v = cl.adam_init(p)
+    lr = 2e-3
+    for t in (1, 2):
+        _, g = tr.loss_grad()
+        cl.adam_step(p, {"w": np.asarray(g, np.float64)}, m, v, t, lr=lr)
+        tr.train(1, lr)
+        got = tr.weights()
+        want = p["w"].astype(np.float32)
+        ulp = np.spacing(np.abs(want))
+        bad = np.abs(got.astype(np.float64) - want) > ulp
+        print(f"[gpu] adam step {t}: max |w_gpu - w_ref| = {np.max(np.abs(got - want)):.3e}, "
+              f"moved {np.max(np.abs(want - w)):.3e}", flush=True)
+        assert not np.any(bad), (t, np.flatnonzero(bad)[:8])
+        assert np.max(np.abs(want.astype(np.float64) - w)) > 0.5 * t * lr   # the step really moved the weights
+
+
 def test_training_fits_one_mode_bath_identity():
     """The linear special case: a one-mode bath is represented exactly by an identity-activation
     closure, and Adam on the GPU drives the normalised loss from about 1 to below 1e-3; the
