@@ -454,6 +454,8 @@ def bench_large3d(args):
     }
     if not args.no_learned:
         out["learned"] = _learned_large3d(args, stream, warmup, steps, value)
+    if not args.no_bath16:
+        out["bath_f16"] = _bath16_large3d(stream, warmup, steps, value)
     if not args.no_cpu_baseline:
         print("[bench] oracle on crops", file=sys.stderr, flush=True)
 
@@ -462,6 +464,47 @@ def bench_large3d(args):
             return configs.config5_3d_large(nx=nx, ny=ny, steps=0)
         out["cpu_baseline"] = cpu_baseline(crop, "16x16x512", "64x64x512", stream=stream.cuda_stream)
     print(json.dumps(out), flush=True)
+
+
+def _bath16_large3d(stream, warmup, steps, v_exp):
+    """The same grid with the bath coordinates stored as binary16 (Y * 1024), a reduced-precision mode reported
+    beside the FP32 line: cell-updates/s, the bath launch against its own algorithmic bytes, and the error the
+    format adds, measured on a 16 x 16 x 512 crop over 2000 steps against the FP32-state run of the same crop
+    (which matches the FP64 oracle to about 1e-6)."""
+    import numpy as np
+    from fdtdb_inputs import configs
+    from paper_2505_23963_amd import Grid
+
+    def layout(nx=512, ny=512, fmt="f16"):
+        p = configs.config5_3d_large(nx=nx, ny=ny, steps=0)
+        if fmt:
+            p.materials[0].bath_storage, p.materials[0].bath_scale = fmt, 1024.0
+        return p
+    p = layout()
+    print(f"[bench] 512^3 with the bath stored as binary16: warm-up {warmup}, timed {steps} steps",
+          file=sys.stderr, flush=True)
+    times, recs, stats = timed_grid(p, stream, warmup, steps)
+    dom = max(recs, key=lambda r: r["ms_total"])
+    avg_ms = dom["ms_total"] / max(dom["launches"], 1)
+    value = p.cells * steps / times[0] / 1e9
+    errs = {}
+    grids = {fmt: Grid(layout(16, 16, fmt), stream=stream.cuda_stream) for fmt in ("f16", None)}
+    for g in grids.values():
+        g.step(2000)
+        g.synchronize()
+    a, b = grids["f16"], grids[None]
+    for name, get in (("E", lambda g: np.concatenate([g.field(c).ravel() for c in range(3)])),
+                      ("H", lambda g: np.concatenate([g.field(c).ravel() for c in range(3, 6)])),
+                      ("P", lambda g: np.concatenate([g.polarization(0, c) for c in range(3)])),
+                      ("Y", lambda g: np.concatenate([g.bath(0, c).ravel() for c in range(3)]))):
+        x, y = get(a), get(b)
+        errs[name] = float(f"{np.linalg.norm(x - y) / np.linalg.norm(y):.3e}")
+    return {"value": round(value, 4), "ms_per_step": round(times[0] / steps * 1e3, 4),
+            "over_fp32_bath": round(value / v_exp, 3), "format": "binary16 of Y * 1024",
+            "bath_kernel_ms": round(avg_ms, 4), "bath_bytes_per_launch": dom["bytes"],
+            "bath_achieved_gbs": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9, 1),
+            "bath_frac_of_hbm_peak": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "rel_l2_vs_fp32_state_16x16x512_2000_steps": errs}
 
 
 def _learned_large3d(args, stream, warmup, steps, v_exp):
@@ -556,6 +599,7 @@ def main():
                     help="closure2d: skip the accuracy runs against the explicit bath (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="large3d: leave out the learned-closure comparison")
+    ap.add_argument("--no-bath16", action="store_true", help="large3d: leave out the 16-bit bath storage line")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from", default=None,
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")

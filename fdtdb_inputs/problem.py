@@ -68,6 +68,9 @@ class LorentzBath:
     width: float = 0.0
     bath_gamma: float = 0.0
     dephasing: float = 0.0
+    # storage of the bath coordinates on the GPU: None (the state type), "f16" or "bf16" of Y * bath_scale
+    bath_storage: Optional[str] = None
+    bath_scale: float = 1.0
 
 
 @dataclass

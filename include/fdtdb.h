@@ -216,6 +216,23 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
  * E_STATE when either grid has stepped, is already paired or holds a learned closure. */
 fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double phase[3]);
 
+/* Storage of a Lorentz-Bath material's bath coordinates Y_j (eq:Yzj_finite_difference; both time
+ * levels): FDTDB_BATH_STATE (the grid's state type, the default), FDTDB_BATH_F16 (IEEE binary16 of
+ * Y_j * scale) or FDTDB_BATH_BF16 (bfloat16 of Y_j * scale).  A reduced-precision mode beside the
+ * method's FP32 state, for baths whose bytes bound the step: the update arithmetic stays FP64, each
+ * new Y_j is rounded to binary32 and then to the 16-bit format (round to nearest even), which halves
+ * the bath's bytes and adds that rounding to every step (its error against the FP64 reference is
+ * measured, not bounded by the FP32 bar).  scale (> 0, a power of two keeps it exact) places the
+ * coordinates in the format's range (binary16: normal from 6.1e-5 to 65504).  Eight coordinates travel
+ * as one 16-byte word ([word][cell] per level and component).  Available for 3D FP32 grids and baths of
+ * 16 modes (the component-split kernel), before the first step, on a
+ * material without a learned closure, outside Bloch pairs, and with no energy monitor over the
+ * material (checked at the first step).  fdtdb_get_bath returns the stored values widened to FP64
+ * and divided by scale.  Errors: E_INVALID (bad format, scale, material or grid), E_STATE (after the
+ * first step, a closure, a Bloch pair). */
+enum { FDTDB_BATH_STATE = 0, FDTDB_BATH_F16 = 1, FDTDB_BATH_BF16 = 2 };
+fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, double scale);
+
 /* -------------------------------------------------------------------------------------- stepping */
 
 /* Enqueue nsteps full time steps on the grid's stream and return without

@@ -489,7 +489,10 @@ struct fdtdb_batch_s {
         if (bytes == 0) bytes = 8;
         hipError_t e = dev_alloc(mem, p, bytes);
         if (e != hipSuccess) return bfail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
+        // zeroing on the null stream, asynchronous to the host: finished before the buffer is used on
+        // the batch's non-blocking stream
         e = hipMemset(*p, 0, bytes);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return bfail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(*p);
         return FDTDB_OK;

@@ -168,6 +168,9 @@ struct EArgs {
     void *hid[3];                    // learned closure hidden state [mcells] of float4
     const float *cw;                 // learned closure weights (FP32, kClosureParams)
     int nterm;                       // multi-term material: terms, each with its levels [term][mcells] in Pcur / Pnew
+    // bath coordinate storage: 0 the state type, 1 binary16 of Y yscale, 2 bfloat16 of Y yscale (yinv = 1 / yscale)
+    int yfmt;
+    double yscale, yinv;
     double cscale[4];                // closure input scales s_E, s_P, s_V and 1 / s_S
     // sources and clock
     const Clock *clock;

@@ -802,6 +802,124 @@ __global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, c
 }
 
 // ---------------------------------------------------------------------------------------------
+// The same update with the bath coordinates stored in 16 bits (a reduced-precision storage mode,
+// reported apart from the FP32 path): YF = 1 IEEE binary16 of Y times a scale s (a power of two keeps
+// the scaling exact), YF = 2 bfloat16 (the upper half of the binary32 pattern) of Y times s.  Eight
+// coordinates (two mode groups) travel as one 16-byte word, so a cell's bath takes half the load
+// instructions of the FP32 layout as well as half the bytes; the arithmetic is FP64 as above, each stored
+// value rounded to binary32 and then to the 16-bit format (round to nearest even at both steps).
+// ---------------------------------------------------------------------------------------------
+typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
+
+template <int YF>
+__device__ __forceinline__ double unpack16(nv4u w, int u, double inv_s) {
+    const unsigned bits = (u & 1) ? (w[u >> 1] >> 16) : (w[u >> 1] & 0xffffu);
+    float f;
+    if constexpr (YF == 1) f = (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
+    else f = __builtin_bit_cast(float, bits << 16);
+    return (double)f * inv_s;
+}
+
+template <int YF>
+__device__ __forceinline__ unsigned pack16(double y, double s) {
+    const float f = (float)(y * s);
+    if constexpr (YF == 1) return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)f);
+    unsigned x = __builtin_bit_cast(unsigned, f);
+    x += 0x7fffu + ((x >> 16) & 1u);                 // round to nearest even on the dropped half
+    return x >> 16;
+}
+
+// NG mode groups of 4 = NG / 2 words of 8 coordinates ([word][cell] per level and component)
+template <typename T, int NG, int C, int YF>
+__device__ __forceinline__ void bath_component16(const EArgs &a, const BathCoef<NG> &cf, int t) {
+    static_assert(NG % 2 == 0, "16-bit bath words hold two mode groups");
+    constexpr int NW = NG / 2;
+    int i, j, k;
+    unflatten<3>(t, a.lo, a.ext, a.ext12, i, j, k);
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const int coord[3] = {i, j, k};
+    const int stride[3] = {s0, s1, 1};
+    const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+    const int mcells = (int)a.mcells;
+    constexpr int a1 = curl_a1(C), a2 = curl_a2(C);
+    const bool has_sig = a.sigma != nullptr;
+    const T *sp = has_sig ? static_cast<const T *>(a.sigma) + m : static_cast<const T *>(a.E[C]) + q;
+    const T sig_raw = *sp;
+    const double t1 = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+    const double t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+    const double Eo = (double)static_cast<const T *>(a.E[C])[q];
+    const double Pc = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pcur[C]) + m);
+    const double Pp = (double)__builtin_nontemporal_load(static_cast<const T *>(a.Pnew[C]) + m);
+    const nv4u *Yc = static_cast<const nv4u *>(a.Ycur[C]);
+    nv4u *Yn = static_cast<nv4u *>(a.Ynew[C]);
+    nv4u yc[NW], yp[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        yc[w] = __builtin_nontemporal_load(Yc + (long long)w * mcells + m);
+        yp[w] = __builtin_nontemporal_load(Yn + (long long)w * mcells + m);
+    }
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    const double sig = has_sig ? (double)sig_raw : a.sigma0;
+    const double inv_s = a.yinv, sc = a.yscale;
+    const double En = Eo + a.inv_eps * (a.dt * (t1 - t2) - (Pc - Pp)) - source_term(a, amp, C, i, j, k);
+    double S = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            S += cf.md[8 * w + u][3] * unpack16<YF>(yc[w], u, inv_s) + cf.md[8 * w + u][4] * unpack16<YF>(yp[w], u, inv_s);
+    }
+    const double Pnew = cf.head[0] * sig * En - cf.head[1] * Pc - cf.head[2] * Pp - S;
+    const double dP = Pnew - Pp;
+    static_cast<T *>(a.E[C])[q] = (T)En;
+    __builtin_nontemporal_store((T)Pnew, static_cast<T *>(a.Pnew[C]) + m);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        unsigned h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            h[u] = pack16<YF>(cf.md[8 * w + u][0] * unpack16<YF>(yc[w], u, inv_s) +
+                                  cf.md[8 * w + u][1] * unpack16<YF>(yp[w], u, inv_s) + cf.md[8 * w + u][2] * dP,
+                              sc);
+        nv4u o;
+        o[0] = h[0] | (h[1] << 16);
+        o[1] = h[2] | (h[3] << 16);
+        o[2] = h[4] | (h[5] << 16);
+        o[3] = h[6] | (h[7] << 16);
+        __builtin_nontemporal_store(o, Yn + (long long)w * mcells + m);
+    }
+}
+
+template <typename T, int NG, int YF>
+__global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c16(const EArgs a, const BathCoef<NG> cf) {
+    const int nbc = gridDim.x / 3;
+    const int c = blockIdx.x / nbc;
+    const int t = (blockIdx.x - c * nbc) * kBathBlock + threadIdx.x;
+    if (t >= a.ext[0] * a.ext12) return;
+    if (c == 0) bath_component16<T, NG, 0, YF>(a, cf, t);
+    else if (c == 1) bath_component16<T, NG, 1, YF>(a, cf, t);
+    else bath_component16<T, NG, 2, YF>(a, cf, t);
+}
+
+// 16-bit bath coordinates widened to FP64 (read-out)
+__global__ __launch_bounds__(kBlock) void k_bath16_to_f64(const unsigned short *src, long long n, int yf, double inv_s,
+                                                          double *dst) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+        const unsigned b = src[i];
+        const float f = yf == 1 ? (float)__builtin_bit_cast(_Float16, (unsigned short)b) : __builtin_bit_cast(float, b << 16);
+        dst[i] = (double)f * inv_s;
+    }
+}
+
+hipError_t launch_bath16_to_f64(const void *src, long long n, int yf, double inv_s, double *dst, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_bath16_to_f64, dim3(g), dim3(kBlock), 0, s, (const unsigned short *)src, n, yf, inv_s, dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
 // H update, generic form
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, bool PML>
@@ -1478,9 +1596,20 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
                 for (int u = 0; u < 5; ++u) cf.md[j][u] = coef_host[kCoefHead + j * kCoefMode + u];
             if (energy)
                 hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a, cf);
-            else if constexpr (DIM == 3 && NC * NG > 6)
-                hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
-                                   dim3(kBathBlock), kBathLdsReserve, s, a, cf);
+            else if constexpr (DIM == 3 && NC * NG > 6) {
+                const dim3 grid(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock));
+                if constexpr (std::is_same<T, float>::value && NG % 2 == 0) {
+                    if (a.yfmt == 1) {
+                        hipLaunchKernelGGL((k_update_e_bath_c16<T, NG, 1>), grid, dim3(kBathBlock), 0, s, a, cf);
+                        return hipGetLastError();
+                    }
+                    if (a.yfmt == 2) {
+                        hipLaunchKernelGGL((k_update_e_bath_c16<T, NG, 2>), grid, dim3(kBathBlock), 0, s, a, cf);
+                        return hipGetLastError();
+                    }
+                }
+                hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), grid, dim3(kBathBlock), kBathLdsReserve, s, a, cf);
+            }
             else
                 hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>),
                                    dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)), dim3(kBlock), 0, s, a, cf);

@@ -30,6 +30,7 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
 hipError_t launch_dft_flux(const double2 *acc, const double2 *acc_im, int npts, int nf, double *flux, hipStream_t s);
 hipError_t launch_nonfinite(bool f64, const void *f, long long n, int *flag, hipStream_t s);
 hipError_t launch_to_f64(bool f64, const void *src, long long n, double *dst, hipStream_t s);
+hipError_t launch_bath16_to_f64(const void *src, long long n, int yf, double inv_s, double *dst, hipStream_t s);
 hipError_t launch_probe(bool f64, const void *E, const void *P, const int *q, const int *m, int n, const Clock *clk,
                         long long capacity, float *outE, float *outP, hipStream_t s);
 }  // namespace fdtdb
@@ -89,6 +90,9 @@ struct Material {
     double cscale[4] = {1.0, 1.0, 1.0, 1.0};
     // FNV-1a of the per-cell sigma values and of the closure weights as given (checkpoint fingerprint)
     uint64_t sigma_hash = 0, weight_hash = 0;
+    // bath coordinate storage: 0 the state type, 1 binary16 or 2 bfloat16 of Y * yscale
+    int yfmt = 0;
+    double yscale = 1.0;
 };
 
 struct Region {
@@ -219,7 +223,11 @@ struct fdtdb_grid_s {
         void *b = nullptr;
         hipError_t e = dev_alloc(mem, &b, bytes + offset);
         if (e != hipSuccess) return fail(FDTDB_E_NOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
+        // the zeroing runs on the null stream, asynchronously to the host; the grid's own stream is
+        // non-blocking, so wait for it here: otherwise a kernel enqueued next on that stream (a
+        // read-out's conversion into a fresh buffer) could run first and then be overwritten
         e = hipMemset(b, 0, bytes + offset);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "hipMemset: %s", hipGetErrorString(e));
         allocs.push_back(b);
         *p = static_cast<char *>(b) + offset;
@@ -475,7 +483,7 @@ void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh
     if (r.mat >= 0) {
         const Material &m = g->mats[r.mat];
         if (m.kind == K_DRUDE) e += 2.0 * ne * w;
-        else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * w;
+        else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * (m.yfmt ? 2.0 : w);
         else if (m.kind == K_CLOSURE) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 2.0 * ne * 16.0;
         else if (m.kind == K_MULTI) e += 3.0 * ne * m.nterm * w;
     }
@@ -530,6 +538,9 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     for (auto &r : g->regions)
         for (auto &e : g->ens)
             if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
+    for (auto &r : g->regions)   // the sampling kernel reads the bath in the state type
+        if (r.energy && r.mat >= 0 && g->mats[r.mat].yfmt)
+            return fail(FDTDB_E_STATE, "an energy monitor covers a bath stored in 16 bits");
     // threads of a region: one per cell, or (vector kernels) one per 4-cell group of the region's
     // fastest-axis range rounded out to whole groups
     auto blocks_of = [&](const Region &r, bool v4) {
@@ -786,6 +797,9 @@ fdtdb_status enqueue_e(fdtdb_grid_s *g) {
                 }
                 a.cw = m.cw_dev;
                 for (int q = 0; q < 4; q++) a.cscale[q] = m.cscale[q];
+                a.yfmt = m.yfmt;
+                a.yscale = m.yscale;
+                a.yinv = 1.0 / m.yscale;
             }
             a.sigma = m.sigma_per_cell ? m.sigma_dev : nullptr;
             a.sigma0 = m.sigma0;
@@ -1011,7 +1025,7 @@ uint64_t fingerprint(const fdtdb_grid_s *g) {
         f.v(m.kind); f.bytes(m.lo, sizeof m.lo); f.bytes(m.hi, sizeof m.hi); f.v(m.eps); f.v(m.omega0);
         f.v(m.gamma0); f.v(m.sigma0); f.v(m.sigma_per_cell); f.v(m.nb); f.vec(m.wj); f.vec(m.gj); f.vec(m.kj);
         f.vec(m.coef); f.v(m.cw_dev != nullptr); f.bytes(m.cscale, sizeof m.cscale);
-        f.v(m.sigma_hash); f.v(m.weight_hash); f.v(m.nterm);
+        f.v(m.sigma_hash); f.v(m.weight_hash); f.v(m.nterm); f.v(m.yfmt); f.v(m.yscale);
     }
     f.v(g->srcs.size());
     for (auto &x : g->srcs) {
@@ -1336,11 +1350,38 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
     return FDTDB_OK;
 }
 
+fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, double scale) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "bath storage is chosen before the first step");
+    if (g->twin || g->orphan) return fail(FDTDB_E_STATE, "16-bit bath storage is not available on Bloch grids");
+    if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH ||
+        g->mats[material_id].nb == 0)
+        return fail(FDTDB_E_INVALID, "the storage format applies to a Lorentz-Bath material's bath");
+    Material &m = g->mats[material_id];
+    if (format < FDTDB_BATH_STATE || format > FDTDB_BATH_BF16) return fail(FDTDB_E_INVALID, "bad storage format");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(FDTDB_E_INVALID, "scale must be finite and > 0");
+    if (m.cw_dev) return fail(FDTDB_E_STATE, "the material's bath is replaced by a learned closure");
+    if (format != FDTDB_BATH_STATE && (g->ndim != 3 || g->f64 || m.ng != 4))
+        return fail(FDTDB_E_INVALID, "16-bit bath storage needs a 3D FP32 grid and 16 bath modes");
+    const size_t word = format == FDTDB_BATH_STATE ? g->esize() : 2;
+    for (int lvl = 0; lvl < 2; lvl++)
+        for (int c = 0; c < 3; c++) {
+            if (!m.Y[lvl][c]) continue;
+            g->release(m.Y[lvl][c]);
+            TRY(g->alloc(&m.Y[lvl][c], (size_t)m.mcells * 4 * m.ng * word, 1024 * (size_t)(3 * lvl + c)));
+        }
+    m.yfmt = format;
+    m.yscale = format == FDTDB_BATH_STATE ? 1.0 : scale;
+    return FDTDB_OK;
+}
+
 fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *weights, int width,
                                     const double *scales) {
     if (!g || !weights || !scales) return fail(FDTDB_E_INVALID, "null argument");
     if (g->finalized) return fail(FDTDB_E_STATE, "closures must be set before the first step");
     if (g->twin || g->orphan) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
+    if (material_id >= 0 && material_id < (int)g->mats.size() && g->mats[material_id].yfmt)
+        return fail(FDTDB_E_STATE, "the closure replaces a bath stored in 16 bits");
     if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH)
         return fail(FDTDB_E_INVALID, "the closure replaces the bath of a Lorentz-Bath material");
     if (width != kClosureWidth) return fail(FDTDB_E_INVALID, "closure width must be %d", kClosureWidth);
@@ -1612,8 +1653,10 @@ fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double *phase)
             return fail(FDTDB_E_INVALID, "a Bloch phase needs a periodic axis of the grid");
     }
     for (const fdtdb_grid_s *g : {re, im})
-        for (auto &m : g->mats)
+        for (auto &m : g->mats) {
             if (m.cw_dev) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
+            if (m.yfmt) return fail(FDTDB_E_STATE, "16-bit bath storage is not available on Bloch grids");
+        }
     if (re->dfts.size() != im->dfts.size()) return fail(FDTDB_E_INVALID, "the parts need the same flux monitors");
     for (size_t i = 0; i < re->dfts.size(); i++) {
         const Dft &a = re->dfts[i], &b = im->dfts[i];
@@ -1818,10 +1861,23 @@ fdtdb_status fdtdb_get_bath(fdtdb_grid g, int mid, int c, int level, double *out
     TRY(sync(g));
     const int slot = (int)((g->steps + level) & 1);
     std::vector<double> tmp((size_t)m.mcells * 4 * m.ng);
-    TRY(read_state(g, m.Y[slot][c], (long long)tmp.size(), tmp.data()));
-    // device layout [group][cell][4] -> [mode][cell]
+    if (m.yfmt) {   // 16-bit storage: widened on the device, scale removed
+        double *d = nullptr;
+        TRY(g->alloc((void **)&d, 8 * tmp.size()));
+        hipError_t e = launch_bath16_to_f64(m.Y[slot][c], (long long)tmp.size(), m.yfmt, 1.0 / m.yscale, d, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e == hipSuccess) e = hipMemcpy(tmp.data(), d, 8 * tmp.size(), hipMemcpyDeviceToHost);
+        void *dv = d;
+        g->release(dv);
+        if (e != hipSuccess) return fail(FDTDB_E_DEVICE, "bath read-out: %s", hipGetErrorString(e));
+    } else {
+        TRY(read_state(g, m.Y[slot][c], (long long)tmp.size(), tmp.data()));
+    }
+    // device layout [group][cell][4] (16-bit storage: [word][cell][8]) -> [mode][cell]
+    const int per = m.yfmt ? 8 : 4;
     for (int jb = 0; jb < m.nb; jb++)
-        for (long long q = 0; q < m.mcells; q++) out[(size_t)jb * m.mcells + q] = tmp[((size_t)(jb / 4) * m.mcells + q) * 4 + (jb & 3)];
+        for (long long q = 0; q < m.mcells; q++)
+            out[(size_t)jb * m.mcells + q] = tmp[((size_t)(jb / per) * m.mcells + q) * per + (jb % per)];
     return FDTDB_OK;
 }
 

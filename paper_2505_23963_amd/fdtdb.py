@@ -65,6 +65,7 @@ SIGNATURES = [
     ("fdtdb_bath_params", C.c_int, [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
                                     _dp, _dp, _dp]),
     ("fdtdb_set_bath_closure", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_int, _dp]),
+    ("fdtdb_set_bath_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double]),
     ("fdtdb_get_closure_state", C.c_int, [C.c_void_p, C.c_int, C.c_int, _dp]),
     ("fdtdb_add_source", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
                                    C.POINTER(C.c_int)]),
@@ -289,6 +290,9 @@ class Grid:
                 sig = _arr(m.sigma_cells)
                 _check(L.fdtdb_set_lorentz_bath(h, C.byref(b), m.omega0, m.gamma0, m.eps_inf, _ptr(sig),
                                                 m.sigma, m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj), C.byref(mid)))
+                if m.bath_storage is not None:
+                    _check(L.fdtdb_set_bath_storage(h, mid.value, {"f16": 1, "bf16": 2}[m.bath_storage],
+                                                    float(m.bath_scale)))
             elif kind == "MultiPole":
                 nt = len(m.kinds)
                 kinds = (C.c_int * nt)(*[{"lorentz": 0, "drude": 1}[k] for k in m.kinds])
