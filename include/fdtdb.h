@@ -356,7 +356,9 @@ fdtdb_status fdtdb_kernel_records(fdtdb_grid g, fdtdb_kernel_record *out, int ca
  * cavity (0: closed ends).  FP64 storage uses 256-thread workgroups. */
 typedef struct fdtdb_batch_s *fdtdb_batch;
 
-/* lengths: ncav cell counts (copied).  Same error model as fdtdb_create_grid. */
+/* lengths: ncav cell counts (copied).  Same error model as fdtdb_create_grid.  Check mode for tests:
+ * with the environment variable FDTDB_POISON_LDS=1 when the batch is created, every LDS word of the
+ * on-chip kernel starts each launch as NaN (results must not change). */
 fdtdb_status fdtdb_batch_create(int ncav, const int64_t *lengths, fdtdb_dtype dtype, double courant, int pml_cells,
                                 double pml_R0, void *hip_stream, fdtdb_batch *out);
 fdtdb_status fdtdb_batch_destroy(fdtdb_batch b);

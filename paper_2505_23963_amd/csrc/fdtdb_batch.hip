@@ -10,6 +10,8 @@
 // FP64 registers, FP32 or FP64 storage, the three-level Lorentz-Bath recurrences.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -68,6 +70,7 @@ struct Args {
     int en_cap, seg_slots;
     const int *seg_slot;                // per segment: its slot index inside its cavity
     long long *clock;                   // index of the next step (advanced by k_batch_tick)
+    int poison;                         // check mode: every LDS word starts as NaN (FDTDB_POISON_LDS=1 at creation)
 };
 
 template <typename T>
@@ -100,6 +103,14 @@ __global__ __launch_bounds__(NT) void k_batch1d(const Args a, const int nsteps, 
     const Seg sg = a.seg[blockIdx.x];
     const Cav cv = a.cav[sg.cav];
     const int t = threadIdx.x;
+    if (a.poison) {   // check mode: a read of an LDS word that no thread of this launch wrote then shows as NaN
+        const double nan = __builtin_nan("");
+        sE[t] = nan;
+        sH[t] = nan;
+        for (int i = t; i < 2 * 256; i += NT) stage[i >> 8][i & 255] = nan;
+        if (t < 3 * (NT / 64)) red[t / (NT / 64)][t % (NT / 64)] = nan;
+        __syncthreads();
+    }
     const int x = sg.x0 - halo + t;
     const bool inside = x >= 0 && x < cv.L;
     const bool own = t >= halo && t < halo + sg.own;
@@ -803,6 +814,9 @@ fdtdb_status fdtdb_batch_create(int ncav, const int64_t *lengths, fdtdb_dtype dt
         b->cavs[c].L = (int)lengths[c];
         b->cavs[c].type.assign(lengths[c], C_VAC);
     }
+    // check mode for tests: LDS filled with NaN at the start of every launch
+    const char *pz = std::getenv("FDTDB_POISON_LDS");
+    b->args.poison = pz && pz[0] == '1';
     if (hip_stream) {
         b->stream = (hipStream_t)hip_stream;
     } else {

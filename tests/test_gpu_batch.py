@@ -153,3 +153,24 @@ def test_batch_retile_after_step_zero_keeps_energy_layout():
     for c in range(3):
         assert np.array_equal(a.energy(c), b.energy(c)), c
         assert np.array_equal(a.field(c, 2), b.field(c, 2)), c
+
+
+@pytest.mark.parametrize("dtype,tiling", [("f32", (32, 512)), ("f64", (16, 256))])
+def test_batch_lds_poisoned_with_nan_changes_nothing(monkeypatch, dtype, tiling):
+    """Check mode (FDTDB_POISON_LDS=1 when the batch is created): every LDS word of the on-chip kernel (the
+    neighbour exchange rows, the DFT staging rows, the energy reduction slots) starts each launch as NaN.
+    Fields, spectra and energy traces stay finite and bitwise equal to a normal run, so no launch reads an
+    LDS word before a thread of that launch wrote it."""
+    from paper_2505_23963_amd import Batch
+    ps = cavities(4, 640, dtype, lengths=[1500, 1777, 2049, 2600])
+    runs = []
+    for poison in ("0", "1"):
+        monkeypatch.setenv("FDTDB_POISON_LDS", poison)
+        b = Batch(ps, tiling=tiling)
+        b.step(640)
+        b.synchronize()
+        runs.append([(b.field(c, 2), b.field(c, 4), b.flux(c), b.energy(c)) for c in range(4)])
+    for plain, poisoned in zip(*runs):
+        for x, y in zip(plain, poisoned):
+            assert np.all(np.isfinite(y))
+            assert np.array_equal(x, y)
