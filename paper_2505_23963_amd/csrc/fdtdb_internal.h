@@ -10,12 +10,13 @@ constexpr int kMaxSources = 4;
 constexpr int kMaxModes = 64;
 constexpr int kMaxEnergy = 4;
 constexpr int kBlock = 256;          // threads per block of the stencil kernels
-// Component-split 3D bath kernel: 128-thread blocks, at most 5 of them per CU (2.5 waves per SIMD),
-// held there by an LDS reservation the kernel does not use (5 x 29 KiB fit the 160 KiB of a CU, 6 do
-// not).  Its register use alone allows 4 waves per SIMD; on the 512^3 layer with N_b = 16 the launch
-// took 6.10 ms against 6.27 ms at 4 waves (256-thread blocks), 6.13 ms at 3 and 6.70 ms at 2.
+// Component-split 3D bath kernel: 128-thread blocks, at most 4 of them per CU (2 waves per SIMD), held
+// there by an LDS reservation the kernel does not use (4 x 36 KiB fit the 160 KiB of a CU, 5 do not).  Its
+// registers allow 4 waves per SIMD, but it streams best with fewer requests in flight: on the 512^3 layer
+// with N_b = 16 (coefficients through scalar loads) 5.77 ms per launch at 2 waves, 5.98 at 2.5, 6.05 at
+// 3, 6.10 at 3.5, 6.21 at 4 (before the scalar-load coefficients: 6.10 at 2.5 and 3 waves, 6.27 at 4).
 constexpr int kBathBlock = 128;
-constexpr unsigned kBathLdsReserve = 29 * 1024;
+constexpr unsigned kBathLdsReserve = 36 * 1024;
 constexpr int kDftSlots = 64;        // steps staged before a DFT flush
 constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
 

@@ -33,8 +33,8 @@ def test_kernel_hash_ignores_comments_but_not_code():
     assert bench.source_hash("E_lorentz_bath_nb8", changed) != base
     # the component-split kernel of the 512^3 workload has its own hash over its own code
     s2 = src.index("void bath_component(const EArgs &a")
-    e2 = src.index("cf.head[1] * Pc", s2)
-    changed2 = src[:e2] + "cf.head[2] * Pc" + src[e2 + len("cf.head[1] * Pc"):]
+    e2 = src.index("co[1] * Pc", s2)
+    changed2 = src[:e2] + "co[2] * Pc" + src[e2 + len("co[1] * Pc"):]
     assert bench.source_hash("E_lorentz_bath_nb16", changed2) != bench.source_hash("E_lorentz_bath_nb16", src)
     assert bench.source_hash("E_lorentz_bath_nb8", changed2) == base
 
