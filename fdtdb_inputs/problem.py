@@ -71,6 +71,11 @@ class LorentzBath:
     # storage of the bath coordinates on the GPU: None (the state type), "f16" or "bf16" of Y * bath_scale
     bath_storage: Optional[str] = None
     bath_scale: float = 1.0
+    # thermal bath: temperature kT (energy units; 0 = none) and the 64-bit seed of its noise
+    kT: float = 0.0
+    noise_seed: int = 0
+    # anharmonic bath: quartic coefficient lambda_j of each mode (None = harmonic)
+    anharmonic: Optional[np.ndarray] = None
 
 
 @dataclass

@@ -75,6 +75,10 @@ def lib():
         L.or_set_P.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
         L.or_set_Y.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp]
         L.or_drive_material.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp, C.c_long, _dp]
+        L.or_set_bath_thermal.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_uint64]
+        L.or_set_bath_anharmonic.argtypes = [C.c_void_p, C.c_int, _dp]
+        _up = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+        L.or_philox.argtypes = [_up, _up, _up]
         L.or_get_dft.argtypes = [C.c_void_p, C.c_int, _dp, C.c_void_p]
         L.or_energy_count.restype = C.c_long
         L.or_energy_count.argtypes = [C.c_void_p, C.c_int]
@@ -167,6 +171,11 @@ class Oracle:
                     self._keep += [wj, gj, kj]
                     rc = L.or_add_lorentz_bath(g, lo, hi, m.omega0, m.gamma0, m.eps_inf, _ptr(sig), m.sigma,
                                                m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj))
+                    if rc == 0 and m.kT:
+                        rc = L.or_set_bath_thermal(g, mi, float(m.kT), int(m.noise_seed))
+                    if rc == 0 and m.anharmonic is not None:
+                        lam = np.ascontiguousarray(m.anharmonic, np.float64)
+                        rc = L.or_set_bath_anharmonic(g, mi, lam)
             elif kind == "MultiPole":
                 kinds = np.array([{"lorentz": 0, "drude": 1}[k] for k in m.kinds], np.int32)
                 rc = L.or_add_multipole(g, lo, hi, m.eps_inf, len(kinds), kinds,
@@ -271,6 +280,13 @@ class Oracle:
     def set_bath(self, mi: int, comp: int, level: int, values: np.ndarray):
         if lib().or_set_Y(self.g, mi, comp, level, np.ascontiguousarray(values, np.float64).ravel()) != 0:
             raise ValueError("no bath")
+
+    @staticmethod
+    def philox(counter, key) -> np.ndarray:
+        """The oracle's own Philox4x32-10 on one counter (4 words) and key (2 words)."""
+        out = np.zeros(4, np.uint32)
+        lib().or_philox(np.ascontiguousarray(counter, np.uint32), np.ascontiguousarray(key, np.uint32), out)
+        return out
 
     def drive(self, mi: int, comp: int, e_seq: np.ndarray) -> np.ndarray:
         """Advance material mi alone under a prescribed E sequence; returns P of its first cell."""

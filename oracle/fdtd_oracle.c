@@ -24,6 +24,27 @@
  *      the scheme ill-posed, so the curl law is followed).
  *   5. monitors: DFT of the plane fields, and the exact discrete energy.
  *
+ * Two extensions of the bath that the paper names as next steps (Sec. V) but
+ * does not write out, taken here in their textbook form:
+ *   * thermal bath: every damped coordinate (P with gamma0, each Y_j with
+ *     gamma_j) gets the Langevin force that the fluctuation-dissipation
+ *     relation pairs with its damping, for the effective mass rho =
+ *     1/(eps0 sigma omega0^2) of eq:H_full: <eta(t) eta(t')> = (2 gamma kT /
+ *     rho) delta(t - t').  Over one step the force is the step average of
+ *     white noise, sqrt(2 gamma kT / (rho dt)) xi, with xi independent, of
+ *     mean zero and unit variance: xi = sqrt(12) (u - 1/2), u uniform from
+ *     the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *     SC'11), counter (cell, step, component, variate / 4), key the seed,
+ *     variate j for bath mode j and variate N_b for P.  Every second moment
+ *     (energies, spectra, equipartition) is that of Gaussian noise.
+ *   * anharmonic bath: a quartic term (rho/4) lambda_j Y_j^4 in each mode's
+ *     potential, i.e. + lambda_j Y_j^3 on the left of eq:EOM_LorentzBath-2,
+ *     taken at level n like omega_j^2 Y_j.
+ * Both enter eq:Yzj_finite_difference as one more term f_j = dt^2 (eta_j -
+ * lambda_j (Y_j^n)^3) / (1 + gamma_j dt / 2), and, through the substitution
+ * of Y_j^{n+1} that gives eq:Pz_update-LB, the P update as - (dt/2) sum_j
+ * k_j f_j and + dt^2 eta_P in its bracket.
+ *
  * Yee placement, cell (i,j,k), z fastest in memory:
  *   Ex (i+1/2,j,k)  Ey (i,j+1/2,k)  Ez (i,j,k+1/2)
  *   Hx (i,j+1/2,k+1/2)  Hy (i+1/2,j,k+1/2)  Hz (i+1/2,j+1/2,k)
@@ -88,6 +109,11 @@ typedef struct {
     int np;
     int pkind[MAXPOLE];
     double pw[MAXPOLE], pg[MAXPOLE], ps[MAXPOLE];   /* omega0 (Drude: omega_p), gamma, sigma */
+    /* thermal / anharmonic bath (Sec. V extensions): kT (0: none), Philox key, quartic coefficients */
+    double kT;
+    uint32_t key[2];
+    double *lam;                      /* nb values, or NULL */
+    long nupd;                        /* updates taken so far: the step index n of the noise */
 } Mat;
 
 typedef struct {
@@ -315,6 +341,53 @@ int or_add_lorentz_bath(void *gp, const long *lo, const long *hi, double omega0,
     return 0;
 }
 
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds on a 4 x 32-bit counter; a round
+ * multiplies counter words 0 and 2 by two fixed constants (full 64-bit products), the new counter is
+ * (hi(word 2 product) ^ word 1 ^ key 0, lo(word 2 product), hi(word 0 product) ^ word 3 ^ key 1,
+ * lo(word 0 product)), and the key is bumped by two Weyl constants before every round but the first. */
+void or_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* the unit-variance variate v of cell q, step n, component c: sqrt(12) (u - 1/2) with
+ * u = (x + 1/2) / 2^32 and x lane v % 4 of Philox(counter (q, n, c, v / 4), key) */
+static double thermal_variate(const Mat *m, long q, long n, int c, int v) {
+    uint32_t ctr[4] = {(uint32_t)q, (uint32_t)n, (uint32_t)c, (uint32_t)(v / 4)}, x[4];
+    or_philox(ctr, m->key, x);
+    double u = ((double)x[v % 4] + 0.5) * (1.0 / 4294967296.0);
+    return (u - 0.5) * 3.4641016151377544;   /* sqrt(12) rounded to double */
+}
+
+/* thermal bath of Lorentz-Bath material mi at temperature kT (energy units, >= 0) with the 64-bit
+ * seed of its noise (key: low word, high word) */
+int or_set_bath_thermal(void *gp, int mi, double kT, uint64_t seed) {
+    Grid *g = (Grid *)gp;
+    if (mi < 0 || mi >= g->nmat || g->m[mi].kind != K_BATH || !(kT >= 0.0) || g->twin) return -1;
+    Mat *m = &g->m[mi];
+    m->kT = kT;
+    m->key[0] = (uint32_t)seed;
+    m->key[1] = (uint32_t)(seed >> 32);
+    return 0;
+}
+
+/* quartic coefficients lambda_j (one per bath mode) of material mi */
+int or_set_bath_anharmonic(void *gp, int mi, const double *lam) {
+    Grid *g = (Grid *)gp;
+    if (mi < 0 || mi >= g->nmat || g->m[mi].kind != K_BATH || g->twin) return -1;
+    Mat *m = &g->m[mi];
+    if (!m->lam) m->lam = zalloc(m->nb);
+    memcpy(m->lam, lam, sizeof(double) * (size_t)m->nb);
+    return 0;
+}
+
 /* Sum of Lorentz and Drude terms in one box (Sec. II.A: realistic susceptibilities are fitted by
  * several such terms): kinds[p] 0 = Lorentz (omega0, gamma, sigma), 1 = Drude (omega_p, gamma); the
  * terms are independent oscillators driven by the same E, and D = eps_inf E + sum_p P_p. */
@@ -537,17 +610,31 @@ static void update_material(Grid *g, Mat *m) {
                         /* eq:Pz_update-LB with the coefficients of eq:Yzj_finite_difference */
                         double w02 = m->omega0 * m->omega0, g0 = m->gamma0, sg = m->sigma[q];
                         double skc = 0.0, bath = 0.0;
+                        /* the thermal and anharmonic term f_j of each mode, and the Langevin force on P */
+                        double f[m->nb > 0 ? m->nb : 1], etaP = 0.0;
+                        long gq = IDX(g, i, j, k);
+                        for (int jb = 0; jb < m->nb; jb++) {
+                            double den = 1.0 + 0.5 * m->gj[jb] * dt, force = 0.0;
+                            if (m->kT > 0.0)
+                                force += sqrt(2.0 * m->gj[jb] * m->kT * w02 * sg / dt) * thermal_variate(m, gq, m->nupd, c, jb);
+                            if (m->lam) {
+                                double y = m->Y[c][0][jb * m->ncell + q];
+                                force -= m->lam[jb] * y * y * y;
+                            }
+                            f[jb] = dt2 * force / den;
+                        }
+                        if (m->kT > 0.0) etaP = sqrt(2.0 * g0 * m->kT * w02 * sg / dt) * thermal_variate(m, gq, m->nupd, c, m->nb);
                         for (int jb = 0; jb < m->nb; jb++) {
                             double den = 1.0 + 0.5 * m->gj[jb] * dt;
                             double aj = (2.0 - m->wj[jb] * m->wj[jb] * dt2) / den;
                             double bj = -2.0 / den;
                             double cj = m->kj[jb] * dt / (2.0 * den);
                             skc += m->kj[jb] * cj;
-                            bath += m->kj[jb] * (aj * m->Y[c][0][jb * m->ncell + q] + bj * m->Y[c][1][jb * m->ncell + q]);
+                            bath += m->kj[jb] * (aj * m->Y[c][0][jb * m->ncell + q] + bj * m->Y[c][1][jb * m->ncell + q] + f[jb]);
                         }
                         double A = 1.0 + 0.5 * g0 * dt + 0.5 * dt * skc;
                         Pnew = (w02 * dt2 * sg * E - (w02 * dt2 - 2.0) * Pn[q] - (1.0 - 0.5 * g0 * dt - 0.5 * dt * skc) * Pm[q]
-                                - 0.5 * dt * bath) / A;
+                                - 0.5 * dt * bath + dt2 * etaP) / A;
                         /* bath oscillators, eq:Yzj_finite_difference; level n-1/2 is overwritten by n+3/2 */
                         for (int jb = 0; jb < m->nb; jb++) {
                             double den = 1.0 + 0.5 * m->gj[jb] * dt;
@@ -555,7 +642,7 @@ static void update_material(Grid *g, Mat *m) {
                             double bj = -2.0 / den;
                             double cj = m->kj[jb] * dt / (2.0 * den);
                             double *y0 = &m->Y[c][0][jb * m->ncell + q], *y1 = &m->Y[c][1][jb * m->ncell + q];
-                            double ynew = aj * (*y0) + (bj + 1.0) * (*y1) + cj * (Pnew - Pm[q]);
+                            double ynew = aj * (*y0) + (bj + 1.0) * (*y1) + cj * (Pnew - Pm[q]) + f[jb];
                             *y1 = *y0;
                             *y0 = ynew;
                         }
@@ -594,6 +681,7 @@ static void update_material(Grid *g, Mat *m) {
                     Pn[q] = Pnew;
                 }
     }
+    m->nupd++;
 }
 
 static void update_H(Grid *g) {
