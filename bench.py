@@ -52,7 +52,7 @@ KERNEL_CODE = {
                             "void k_update_e_bath_c(const EArgs a"),
 }
 # rocprofv3 kernel-name patterns of the counted kernels
-KERNEL_NAMES = {"k_update_e_bath<3, float, 2,": "E_lorentz_bath_nb8", "k_update_e_bath_c<float, 4>": "E_lorentz_bath_nb16"}
+KERNEL_NAMES = {"k_update_e_bath<3, float, 2,": "E_lorentz_bath_nb8", "k_update_e_bath_c<float, 4, false>": "E_lorentz_bath_nb16"}
 
 
 def source_hash(tag: str = "E_lorentz_bath_nb16", src: str = None) -> str:
@@ -456,6 +456,8 @@ def bench_large3d(args):
         out["learned"] = _learned_large3d(args, stream, warmup, steps, value)
     if not args.no_bath16:
         out["bath_f16"] = _bath16_large3d(stream, warmup, steps, value)
+    if not args.no_thermal:
+        out["thermal"] = _thermal_large3d(stream, warmup, steps, value)
     if not args.no_cpu_baseline:
         print("[bench] oracle on crops", file=sys.stderr, flush=True)
 
@@ -505,6 +507,27 @@ def _bath16_large3d(stream, warmup, steps, v_exp):
             "bath_achieved_gbs": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9, 1),
             "bath_frac_of_hbm_peak": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "rel_l2_vs_fp32_state_16x16x512_2000_steps": errs}
+
+
+def _thermal_large3d(stream, warmup, steps, v_exp):
+    """The same grid with its bath made thermal (Langevin forces at kT = 1e-6, Philox noise) and anharmonic
+    (lambda_j = 50): cell-updates/s and the bath launch against its algorithmic bytes (the same 648 B per
+    cell: the noise is generated in registers).  Its parity against the oracle is that of the thermal tests
+    (FP64 1e-12, FP32 1e-5 on a crop of this layout with this set-up)."""
+    from fdtdb_inputs import configs
+    p = configs.thermal_setup(configs.config5_3d_large(steps=0))
+    m = p.materials[0]
+    print(f"[bench] 512^3 thermal + anharmonic bath: warm-up {warmup}, timed {steps} steps", file=sys.stderr, flush=True)
+    times, recs, _ = timed_grid(p, stream, warmup, steps)
+    dom = max(recs, key=lambda r: r["ms_total"])
+    avg_ms = dom["ms_total"] / max(dom["launches"], 1)
+    value = p.cells * steps / times[0] / 1e9
+    return {"value": round(value, 4), "ms_per_step": round(times[0] / steps * 1e3, 4),
+            "over_plain_bath": round(value / v_exp, 3), "kT": m.kT, "lambda_j": float(m.anharmonic[0]),
+            "bath_kernel_ms": round(avg_ms, 4), "bath_bytes_per_launch": dom["bytes"],
+            "bath_achieved_gbs": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9, 1),
+            "bath_frac_of_hbm_peak": round(dom["bytes"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "parity": "tests/test_gpu_thermal.py"}
 
 
 def _learned_large3d(args, stream, warmup, steps, v_exp):
@@ -600,6 +623,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="large3d: leave out the learned-closure comparison")
     ap.add_argument("--no-bath16", action="store_true", help="large3d: leave out the 16-bit bath storage line")
+    ap.add_argument("--no-thermal", action="store_true", help="large3d: leave out the thermal / anharmonic bath line")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from", default=None,
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")

@@ -180,6 +180,14 @@ def config5_3d_large(nx: int = 512, ny: int = 512, steps: int = 4000, nb: int = 
     return p
 
 
+def thermal_setup(p: Problem, kT: float = 1e-6, lam: float = 50.0, seed: int = 0x2505_23963) -> Problem:
+    """The large 3D layout with its Lorentz-Bath slab made thermal (temperature kT, noise seed) and
+    anharmonic (quartic coefficient lam on every mode): the thermal / anharmonic benchmark line."""
+    m = p.materials[0]
+    m.kT, m.noise_seed, m.anharmonic = kT, seed, np.full(m.n_bath, lam)
+    return p
+
+
 # ----------------------------------------------------------------------------------------------
 # learned closure: seeded initial weights (stream 5)
 # ----------------------------------------------------------------------------------------------

@@ -213,7 +213,8 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
  * so the energy-growth watchdog is off on pairs).  Bloch grids run the generic per-cell kernels.
  * Destroying one part leaves the other unable to step (E_STATE).  Errors: E_INVALID for mismatched
  * grids, a phase on a non-periodic axis or a flux plane normal to a Bloch axis at its first cell;
- * E_STATE when either grid has stepped, is already paired or holds a learned closure. */
+ * E_STATE when either grid has stepped, is already paired or holds a learned closure, a bath stored
+ * in 16 bits or a thermal or anharmonic bath. */
 fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double phase[3]);
 
 /* Storage of a Lorentz-Bath material's bath coordinates Y_j (eq:Yzj_finite_difference; both time
@@ -232,6 +233,33 @@ fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double phase[3
  * first step, a closure, a Bloch pair). */
 enum { FDTDB_BATH_STATE = 0, FDTDB_BATH_F16 = 1, FDTDB_BATH_BF16 = 2 };
 fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, double scale);
+
+/* Thermal bath: the extension the paper names in its outlook (Sec. V, thermal effects in the bath
+ * oscillators), taken as Langevin forces.  Every damped coordinate of Lorentz-Bath material
+ * material_id (P with gamma0, each Y_j with gamma_j) receives the force that fluctuation-dissipation
+ * pairs with its damping for the effective mass rho = 1 / (eps0 sigma omega0^2) of eq:H_full, so that
+ * the matter relaxes to the Gibbs state at temperature kT (energy units, same as the fields').  Over
+ * one step the force is sqrt(2 gamma kT / (rho dt)) xi with xi = sqrt(12) (u - 1/2), u = (x + 1/2) /
+ * 2^32, x a 32-bit word of Philox4x32-10 with counter (linear cell index of the grid, step index n,
+ * E component, variate / 4) and key (seed low word, seed high word), lane variate % 4; bath mode j
+ * takes variate j and P variate N_b.  It enters eq:Yzj_finite_difference as + dt^2 eta_j /
+ * (1 + gamma_j dt / 2) and, through the substituted Y_j^{n+1}, eq:Pz_update-LB (and P's own force as
+ * + dt^2 eta_P in its bracket).  kT = 0 removes it.  The noise depends only on (seed, cell, step,
+ * component), so runs, checkpoints and resumes are reproducible.  Before the first step; a real grid
+ * (not a Bloch pair), bath kept in the state type (not 16-bit storage), no learned closure.  Such a
+ * material runs on the general E kernel.  Errors: E_INVALID (kT < 0 or not finite, not a Lorentz-Bath
+ * material with a bath), E_STATE (after the first step, Bloch pair, 16-bit storage, closure). */
+fdtdb_status fdtdb_set_bath_thermal(fdtdb_grid g, int material_id, double kT, uint64_t seed);
+
+/* Anharmonic bath (Sec. V outlook, anharmonicity in the bath oscillators): a quartic term
+ * (rho / 4) lambda_j Y_j^4 in the potential of each bath mode, i.e. + lambda_j Y_j^3 on the left of
+ * eq:EOM_LorentzBath-2, taken at level n like omega_j^2 Y_j: eq:Yzj_finite_difference gains
+ * - dt^2 lambda_j (Y_j^n)^3 / (1 + gamma_j dt / 2), and eq:Pz_update-LB the same term through the
+ * substituted Y_j^{n+1}.  lambda: host array of n = N_b values (copied); n = 0 returns to the harmonic
+ * bath.  No stability bound is checked for it (the recurrence is nonlinear).  An energy monitor over
+ * such a material is refused at the first step (its sum is the harmonic one).  Conditions and errors as
+ * for fdtdb_set_bath_thermal, and E_INVALID when n is neither 0 nor N_b or a value is not finite. */
+fdtdb_status fdtdb_set_bath_anharmonic(fdtdb_grid g, int material_id, const double *lambda, int n);
 
 /* -------------------------------------------------------------------------------------- stepping */
 

@@ -172,6 +172,12 @@ struct EArgs {
     // bath coordinate storage: 0 the state type, 1 binary16 of Y yscale, 2 bfloat16 of Y yscale (yinv = 1 / yscale)
     int yfmt;
     double yscale, yinv;
+    // thermal (bit 0) and anharmonic (bit 1) bath: extension block of the coefficient table after the
+    // modes (per mode: noise amplitude per sqrt(sigma), quartic coefficient, share in the P update;
+    // head slot 6: P's noise amplitude per sqrt(sigma)); key of the noise generator
+    int bext;
+    unsigned key0, key1;
+    int nb;                          // bath modes of the material (the table pads to 4 per group)
     double cscale[4];                // closure input scales s_E, s_P, s_V and 1 / s_S
     // sources and clock
     const Clock *clock;
@@ -229,12 +235,17 @@ struct BathCoef {
 // Coefficient table layout of a bath / Lorentz material (FP64):
 //   [0] cE = w0^2 dt^2 / A      [1] cP = (w0^2 dt^2 - 2) / A
 //   [2] cPm = (1 - g0 dt/2 - (dt/2) sum k c) / A
-//   [3] rho0 = 1 / w0^2 (energy; rho = rho0 / sigma)   [4] w0^2   [5..7] unused
+//   [3] rho0 = 1 / w0^2 (energy; rho = rho0 / sigma)   [4] w0^2   [5] 1 / A
+//   [6] thermal bath: dt^2 sqrt(2 g0 kT w0^2 / dt) / A, P's noise amplitude per sqrt(sigma)   [7] unused
 //   then per mode j (stride 8): a_j, b_j + 1, c_j, sa_j, sb_j, w_j^2, unused, unused
-//   with sa_j = (dt/2) k_j a_j / A and sb_j = (dt/2) k_j b_j / A.
+//   with sa_j = (dt/2) k_j a_j / A and sb_j = (dt/2) k_j b_j / A;
+//   then, for a thermal or anharmonic bath, per mode j (stride kCoefExt): the noise amplitude per
+//   sqrt(sigma) dt^2 sqrt(2 g_j kT w0^2 / dt) / den_j, the quartic coefficient lambda_j dt^2 / den_j
+//   (den_j = 1 + g_j dt / 2), and the share (dt/2) k_j / A of the mode's extra term in the P update.
 // Drude table: [0] dE = wp^2 dt^2 / (1 + g dt/2)  [1] dV = (1 - g dt/2)/(1 + g dt/2)  [2] rho = 1/wp^2.
 constexpr int kCoefHead = 8;
 constexpr int kCoefMode = 8;
+constexpr int kCoefExt = 3;          // per mode in the extension block of a thermal / anharmonic bath
 
 // Device memory source of a grid, batch or trainer: the process-wide allocator at the object's
 // creation (null callbacks: hipMalloc / hipFree).  Blocks are required to be 256-byte aligned.

@@ -115,6 +115,30 @@ __device__ __forceinline__ double at_plus_bloch(const void *f, const void *tw, i
 
 typedef const __attribute__((address_space(4))) float *cfptr;
 
+// Thermal bath noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), ten rounds on a 4-word
+// counter; each round multiplies words 0 and 2 by fixed constants (high and low halves of the 64-bit
+// products), mixes the high halves with words 1 and 3 and the key, and the key advances by two Weyl
+// constants between rounds.  Counter (grid cell, step, component, variate / 4), key the material's
+// seed: variate v is lane v % 4, mode j takes v = j and P takes v = N_b.
+struct Philox4 { unsigned x[4]; };
+__device__ __forceinline__ Philox4 philox4x32_10(unsigned c0, unsigned c1, unsigned c2, unsigned c3, unsigned k0,
+                                                 unsigned k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        // one 64-bit product per word (a single multiply instruction instead of a high and a low one)
+        const unsigned long long p0 = 0xD2511F53ull * c0, p1 = 0xCD9E8D57ull * c2;
+        c0 = (unsigned)(p1 >> 32) ^ c1 ^ k0; c1 = (unsigned)p1; c2 = (unsigned)(p0 >> 32) ^ c3 ^ k1; c3 = (unsigned)p0;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+// unit-variance variate of a 32-bit word: sqrt(12) (u - 1/2), u = (x + 1/2) / 2^32, computed as
+// (x - (2^31 - 1/2)) (sqrt(12) 2^-32): the difference is exact and the constant is sqrt(12) rounded
+// to double times a power of two, so the one rounded product is the same value
+__device__ __forceinline__ double unit_variate(unsigned x) {
+    return ((double)x - 2147483647.5) * (3.4641016151377544 / 4294967296.0);
+}
+
 // soft-current term dt J(t_n) profile / eps of component c at cell (i, j, k)
 __device__ __forceinline__ double source_term(const EArgs &a, const double *amp, int c, int i, int j, int k) {
     double s = 0.0;
@@ -404,7 +428,8 @@ __global__ __launch_bounds__(kBlock) void k_update_e_closure(const EArgs a) {
 
 
 // ---------------------------------------------------------------------------------------------
-template <int DIM, typename T, int KIND, int NG, bool PML, bool ENERGY>
+// EXT (K_BATH only): the thermal / anharmonic terms of an extended bath
+template <int DIM, typename T, int KIND, int NG, bool PML, bool ENERGY, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
     using V4 = vec4_t<T>;
     RegV R;
@@ -524,17 +549,59 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                     S += md[2 * kCoefMode + 3] * (double)yc[g].z + md[2 * kCoefMode + 4] * (double)yp[g].z;
                     S += md[3 * kCoefMode + 3] * (double)yc[g].w + md[3 * kCoefMode + 4] * (double)yp[g].w;
                 }
-                const double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - S;
+                // thermal / anharmonic bath: each mode's extra term f_j (Langevin force and quartic force,
+                // times dt^2 / den_j) enters its own update and, through the substituted Y_j^{n+1}, the
+                // P update with the share (dt/2) k_j / A; P's own Langevin force is added to P.  The terms of
+                // a group are computed where used (twice: for P, then for Y), not held for all modes.
+                constexpr bool ext = NG > 0 && EXT;
+                const double *xt = cf + kCoefHead + 4 * NG * kCoefMode;
+                const double r = (a.bext & 1) ? sqrt(sig) : 0.0;
+                const unsigned step = ext ? (unsigned)a.clock->step : 0u;
+                auto ext_terms = [&](int g, double *f) {
+                    Philox4 w{};
+                    if (a.bext & 1) w = philox4x32_10((unsigned)q, step, (unsigned)c, (unsigned)g, a.key0, a.key1);
+                    const double yv[4] = {(double)yc[g].x, (double)yc[g].y, (double)yc[g].z, (double)yc[g].w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double *x = xt + (4 * g + u) * kCoefExt;
+                        f[u] = (a.bext & 1) ? x[0] * r * unit_variate(w.x[u]) : 0.0;
+                        if (a.bext & 2) f[u] -= x[1] * yv[u] * yv[u] * yv[u];
+                    }
+                };
+                double Pnew = cf[0] * sig * En - cf[1] * Pc - cf[2] * Pp - S;
+                if constexpr (ext) {
+                    double fs = 0.0;
+#pragma unroll
+                    for (int g = 0; g < NG; ++g) {
+                        double f[4];
+                        ext_terms(g, f);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) fs += xt[(4 * g + u) * kCoefExt + 2] * f[u];
+                    }
+                    Pnew -= fs;
+                    if ((a.bext & 1) && cf[6] != 0.0) {      // P's own force (none without gamma0)
+                        const int v = a.nb;
+                        const Philox4 w = philox4x32_10((unsigned)q, step, (unsigned)c, (unsigned)(v >> 2), a.key0, a.key1);
+                        Pnew += cf[6] * r * unit_variate(w.x[v & 3]);
+                    }
+                }
                 Pn_[m] = (T)Pnew;
                 const double dP = Pnew - Pp;
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     const double *md = cf + kCoefHead + 4 * g * kCoefMode;
+                    double y[4] = {md[0 * kCoefMode + 0] * (double)yc[g].x + md[0 * kCoefMode + 1] * (double)yp[g].x + md[0 * kCoefMode + 2] * dP,
+                                   md[1 * kCoefMode + 0] * (double)yc[g].y + md[1 * kCoefMode + 1] * (double)yp[g].y + md[1 * kCoefMode + 2] * dP,
+                                   md[2 * kCoefMode + 0] * (double)yc[g].z + md[2 * kCoefMode + 1] * (double)yp[g].z + md[2 * kCoefMode + 2] * dP,
+                                   md[3 * kCoefMode + 0] * (double)yc[g].w + md[3 * kCoefMode + 1] * (double)yp[g].w + md[3 * kCoefMode + 2] * dP};
+                    if constexpr (ext) {
+                        double f[4];
+                        ext_terms(g, f);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) y[u] += f[u];
+                    }
                     V4 o;
-                    o.x = (T)(md[0 * kCoefMode + 0] * (double)yc[g].x + md[0 * kCoefMode + 1] * (double)yp[g].x + md[0 * kCoefMode + 2] * dP);
-                    o.y = (T)(md[1 * kCoefMode + 0] * (double)yc[g].y + md[1 * kCoefMode + 1] * (double)yp[g].y + md[1 * kCoefMode + 2] * dP);
-                    o.z = (T)(md[2 * kCoefMode + 0] * (double)yc[g].z + md[2 * kCoefMode + 1] * (double)yp[g].z + md[2 * kCoefMode + 2] * dP);
-                    o.w = (T)(md[3 * kCoefMode + 0] * (double)yc[g].w + md[3 * kCoefMode + 1] * (double)yp[g].w + md[3 * kCoefMode + 2] * dP);
+                    o.x = (T)y[0]; o.y = (T)y[1]; o.z = (T)y[2]; o.w = (T)y[3];
                     Yn[(long long)g * a.mcells + m] = o;
                 }
                 if (ENERGY && sample) {
@@ -758,7 +825,9 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
 // they are re-read through the scalar cache where used (by value they overflow the scalar registers
 // and are read back lane by lane): 512^3 bath launch 6.00 against 6.13 ms.
 // ---------------------------------------------------------------------------------------------
-template <typename T, int NG, int C>
+// EXT: thermal / anharmonic bath (the extra term f_j of each mode and P's Langevin force, as in the
+// general kernel; noise counter (cell, step, component, group))
+template <typename T, int NG, int C, bool EXT>
 __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG> &cf, int t) {
     using V4 = nvec4_t<T>;
     int i, j, k;
@@ -801,7 +870,36 @@ __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG
         for (int u = 0; u < 4; ++u) S += md[u * kCoefMode + 3] * (double)yc[g][u] + md[u * kCoefMode + 4] * (double)yp[g][u];
     }
     asm volatile("" : "+s"(co));
-    const double Pnew = co[0] * sig * En - co[1] * Pc - co[2] * Pp - S;
+    double Pnew = co[0] * sig * En - co[1] * Pc - co[2] * Pp - S;
+    double fx[EXT ? 4 * NG : 1];
+    if constexpr (EXT) {
+        const double r = (a.bext & 1) ? sqrt(sig) : 0.0;
+        const unsigned step = (unsigned)a.clock->step;
+        double fs = 0.0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            Philox4 w{};
+            if (a.bext & 1) w = philox4x32_10((unsigned)q, step, (unsigned)C, (unsigned)g, a.key0, a.key1);
+            asm volatile("" : "+s"(co));
+            const cdp xt = co + kCoefHead + 4 * NG * kCoefMode + 4 * g * kCoefExt;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double y = (double)yc[g][u];
+                double f = 0.0;
+                if (a.bext & 1) f = xt[u * kCoefExt + 0] * r * unit_variate(w.x[u]);
+                if (a.bext & 2) f -= xt[u * kCoefExt + 1] * y * y * y;
+                fx[4 * g + u] = f;
+                fs += xt[u * kCoefExt + 2] * f;
+            }
+        }
+        Pnew -= fs;
+        asm volatile("" : "+s"(co));
+        if ((a.bext & 1) && co[6] != 0.0) {      // P's own force (none without gamma0)
+            const int v = a.nb;
+            const Philox4 w = philox4x32_10((unsigned)q, step, (unsigned)C, (unsigned)(v >> 2), a.key0, a.key1);
+            Pnew += co[6] * r * unit_variate(w.x[v & 3]);
+        }
+    }
     const double dP = Pnew - Pp;
     static_cast<T *>(a.E[C])[q] = (T)En;
     __builtin_nontemporal_store((T)Pnew, static_cast<T *>(a.Pnew[C]) + m);
@@ -811,13 +909,16 @@ __device__ __forceinline__ void bath_component(const EArgs &a, const BathCoef<NG
         const cdp md = co + kCoefHead + 4 * g * kCoefMode;
         V4 o;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            o[u] = (T)(md[u * kCoefMode + 0] * (double)yc[g][u] + md[u * kCoefMode + 1] * (double)yp[g][u] + md[u * kCoefMode + 2] * dP);
+        for (int u = 0; u < 4; ++u) {
+            double v = md[u * kCoefMode + 0] * (double)yc[g][u] + md[u * kCoefMode + 1] * (double)yp[g][u] + md[u * kCoefMode + 2] * dP;
+            if constexpr (EXT) v += fx[4 * g + u];
+            o[u] = (T)v;
+        }
         __builtin_nontemporal_store(o, Yn + (long long)g * mcells + m);
     }
 }
 
-template <typename T, int NG>
+template <typename T, int NG, bool EXT>
 __global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, const BathCoef<NG> cf) {
     // blocks in launch order within a component (every XCD streaming next to the others): on the 512^3
     // layer 6.30 ms against 6.33 ms with a contiguous share of the component per XCD
@@ -825,9 +926,9 @@ __global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, c
     const int c = blockIdx.x / nbc;
     const int t = (blockIdx.x - c * nbc) * kBathBlock + threadIdx.x;
     if (t >= a.ext[0] * a.ext12) return;
-    if (c == 0) bath_component<T, NG, 0>(a, cf, t);
-    else if (c == 1) bath_component<T, NG, 1>(a, cf, t);
-    else bath_component<T, NG, 2>(a, cf, t);
+    if (c == 0) bath_component<T, NG, 0, EXT>(a, cf, t);
+    else if (c == 1) bath_component<T, NG, 1, EXT>(a, cf, t);
+    else bath_component<T, NG, 2, EXT>(a, cf, t);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1627,9 +1728,22 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
     constexpr int NC = DIM == 3 ? 3 : 1;
-    // the specialised bath kernels read no other part: real grids only (a Bloch pair takes k_update_e)
+    // the specialised bath kernels read no other part: real grids only (a Bloch pair takes k_update_e);
+    // of them only the component-split kernel carries the thermal / anharmonic terms (without energy
+    // sampling), other extended baths take k_update_e
+    if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16 && DIM == 3 && NC * NG > 6) {
+        if (!a.bloch && a.bext && !energy) {
+            // no occupancy cap: with the noise generator the kernel is bound by its arithmetic as much as by
+            // its bytes and runs best at its register limit of 3 waves per SIMD (512^3 layer 6.26 ms,
+            // 7.45 ms at 2.5 waves, 9.37 ms at 2; bounding it to 4 waves would spill 47 registers)
+            BathCoef<NG> cf{};
+            hipLaunchKernelGGL((k_update_e_bath_c<T, NG, true>), dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
+                               dim3(kBathBlock), 0, s, a, cf);
+            return hipGetLastError();
+        }
+    }
     if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16) {
-        if (!a.bloch) {
+        if (!a.bloch && !a.bext) {
             BathCoef<NG> cf;
             for (int h = 0; h < 3; ++h) cf.head[h] = coef_host[h];
             for (int j = 0; j < 4 * NG; ++j)
@@ -1648,11 +1762,20 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
                         return hipGetLastError();
                     }
                 }
-                hipLaunchKernelGGL((k_update_e_bath_c<T, NG>), grid, dim3(kBathBlock), kBathLdsReserve, s, a, cf);
+                hipLaunchKernelGGL((k_update_e_bath_c<T, NG, false>), grid, dim3(kBathBlock), kBathLdsReserve, s, a, cf);
             }
             else
                 hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>),
                                    dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)), dim3(kBlock), 0, s, a, cf);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (KIND == K_BATH && NG > 0 && !PML) {
+        if (a.bext) {
+            if (energy)
+                hipLaunchKernelGGL((k_update_e<DIM, T, KIND, NG, PML, true, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_update_e<DIM, T, KIND, NG, PML, false, true>), dim3(nblocks(n)), dim3(kBlock), 0, s, a);
             return hipGetLastError();
         }
     }

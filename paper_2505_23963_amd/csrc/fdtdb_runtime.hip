@@ -93,6 +93,11 @@ struct Material {
     // bath coordinate storage: 0 the state type, 1 binary16 or 2 bfloat16 of Y * yscale
     int yfmt = 0;
     double yscale = 1.0;
+    // thermal bath (kT > 0, noise key from seed) and anharmonic bath (lam, one per mode)
+    double kT = 0.0;
+    uint64_t seed = 0;
+    std::vector<double> lam;
+    int bext() const { return (kT > 0.0 ? 1 : 0) | (lam.empty() ? 0 : 2); }
 };
 
 struct Region {
@@ -538,9 +543,12 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
     for (auto &r : g->regions)
         for (auto &e : g->ens)
             if (region_hits_box(r, e.lo, e.hi)) r.energy = true;
-    for (auto &r : g->regions)   // the sampling kernel reads the bath in the state type
+    for (auto &r : g->regions) {  // the sampling kernel reads the bath in the state type
         if (r.energy && r.mat >= 0 && g->mats[r.mat].yfmt)
             return fail(FDTDB_E_STATE, "an energy monitor covers a bath stored in 16 bits");
+        if (r.energy && r.mat >= 0 && !g->mats[r.mat].lam.empty())
+            return fail(FDTDB_E_STATE, "an energy monitor covers an anharmonic bath (its sum is the harmonic one)");
+    }
     // threads of a region: one per cell, or (vector kernels) one per 4-cell group of the region's
     // fastest-axis range rounded out to whole groups
     auto blocks_of = [&](const Region &r, bool v4) {
@@ -800,6 +808,10 @@ fdtdb_status enqueue_e(fdtdb_grid_s *g) {
                 a.yfmt = m.yfmt;
                 a.yscale = m.yscale;
                 a.yinv = 1.0 / m.yscale;
+                a.nb = m.nb;
+                a.bext = kind == K_BATH ? m.bext() : 0;
+                a.key0 = (unsigned)m.seed;
+                a.key1 = (unsigned)(m.seed >> 32);
             }
             a.sigma = m.sigma_per_cell ? m.sigma_dev : nullptr;
             a.sigma0 = m.sigma0;
@@ -1026,6 +1038,7 @@ uint64_t fingerprint(const fdtdb_grid_s *g) {
         f.v(m.gamma0); f.v(m.sigma0); f.v(m.sigma_per_cell); f.v(m.nb); f.vec(m.wj); f.vec(m.gj); f.vec(m.kj);
         f.vec(m.coef); f.v(m.cw_dev != nullptr); f.bytes(m.cscale, sizeof m.cscale);
         f.v(m.sigma_hash); f.v(m.weight_hash); f.v(m.nterm); f.v(m.yfmt); f.v(m.yscale);
+        f.v(m.kT); f.v(m.seed); f.vec(m.lam);
     }
     f.v(g->srcs.size());
     for (auto &x : g->srcs) {
@@ -1350,6 +1363,66 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
     return FDTDB_OK;
 }
 
+// Extension block of the coefficient table of a thermal or anharmonic bath (layout with the table's)
+static fdtdb_status rebuild_ext(fdtdb_grid_s *g, Material &m) {
+    const double dt = g->dt, w02 = m.omega0 * m.omega0;
+    const size_t base = kCoefHead + (size_t)kCoefMode * 4 * m.ng;
+    double skc = 0.0;
+    for (int jb = 0; jb < m.nb; jb++) skc += m.kj[jb] * (m.kj[jb] * dt / (2.0 * (1.0 + 0.5 * m.gj[jb] * dt)));
+    const double A = 1.0 + 0.5 * m.gamma0 * dt + 0.5 * dt * skc;
+    m.coef.resize(base);
+    m.coef[6] = 0.0;
+    if (m.bext()) {
+        m.coef.resize(base + (size_t)kCoefExt * 4 * m.ng, 0.0);
+        if (m.kT > 0.0) m.coef[6] = dt * dt * std::sqrt(2.0 * m.gamma0 * m.kT * w02 / dt) / A;
+        for (int jb = 0; jb < m.nb; jb++) {
+            const double den = 1.0 + 0.5 * m.gj[jb] * dt;
+            double *x = &m.coef[base + (size_t)kCoefExt * jb];
+            x[0] = m.kT > 0.0 ? dt * dt * std::sqrt(2.0 * m.gj[jb] * m.kT * w02 / dt) / den : 0.0;
+            x[1] = m.lam.empty() ? 0.0 : m.lam[jb] * dt * dt / den;
+            x[2] = 0.5 * dt * m.kj[jb] / A;
+        }
+    }
+    void *old = m.coef_dev;
+    g->release(old);
+    m.coef_dev = nullptr;
+    TRY(g->alloc((void **)&m.coef_dev, 8 * m.coef.size()));
+    HIP_TRY(hipMemcpy(m.coef_dev, m.coef.data(), 8 * m.coef.size(), hipMemcpyHostToDevice));
+    return FDTDB_OK;
+}
+
+static fdtdb_status ext_target(fdtdb_grid g, int material_id) {
+    if (!g) return fail(FDTDB_E_INVALID, "null grid");
+    if (g->finalized) return fail(FDTDB_E_STATE, "thermal and anharmonic terms are set before the first step");
+    if (g->twin || g->orphan) return fail(FDTDB_E_STATE, "thermal and anharmonic baths are not available on Bloch grids");
+    if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH ||
+        g->mats[material_id].nb == 0)
+        return fail(FDTDB_E_INVALID, "thermal and anharmonic terms apply to a Lorentz-Bath material's bath");
+    if (g->mats[material_id].yfmt) return fail(FDTDB_E_STATE, "the bath is stored in 16 bits");
+    if (g->mats[material_id].cw_dev) return fail(FDTDB_E_STATE, "the material's bath is replaced by a learned closure");
+    return FDTDB_OK;
+}
+
+fdtdb_status fdtdb_set_bath_thermal(fdtdb_grid g, int material_id, double kT, uint64_t seed) {
+    TRY(ext_target(g, material_id));
+    if (!(kT >= 0.0) || !std::isfinite(kT)) return fail(FDTDB_E_INVALID, "kT must be finite and >= 0");
+    Material &m = g->mats[material_id];
+    m.kT = kT;
+    m.seed = seed;
+    return rebuild_ext(g, m);
+}
+
+fdtdb_status fdtdb_set_bath_anharmonic(fdtdb_grid g, int material_id, const double *lambda, int n) {
+    TRY(ext_target(g, material_id));
+    Material &m = g->mats[material_id];
+    if (n != 0 && (!lambda || n != m.nb)) return fail(FDTDB_E_INVALID, "one quartic coefficient per bath mode (%d)", m.nb);
+    for (int jb = 0; jb < n; jb++)
+        if (!std::isfinite(lambda[jb])) return fail(FDTDB_E_INVALID, "non-finite quartic coefficient");
+    if (n) m.lam.assign(lambda, lambda + n);
+    else m.lam.clear();
+    return rebuild_ext(g, m);
+}
+
 fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, double scale) {
     if (!g) return fail(FDTDB_E_INVALID, "null grid");
     if (g->finalized) return fail(FDTDB_E_STATE, "bath storage is chosen before the first step");
@@ -1361,6 +1434,7 @@ fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, d
     if (format < FDTDB_BATH_STATE || format > FDTDB_BATH_BF16) return fail(FDTDB_E_INVALID, "bad storage format");
     if (!(scale > 0.0) || !std::isfinite(scale)) return fail(FDTDB_E_INVALID, "scale must be finite and > 0");
     if (m.cw_dev) return fail(FDTDB_E_STATE, "the material's bath is replaced by a learned closure");
+    if (m.bext()) return fail(FDTDB_E_STATE, "a thermal or anharmonic bath is kept in the state type");
     if (format != FDTDB_BATH_STATE && (g->ndim != 3 || g->f64 || m.ng != 4))
         return fail(FDTDB_E_INVALID, "16-bit bath storage needs a 3D FP32 grid and 16 bath modes");
     const size_t word = format == FDTDB_BATH_STATE ? g->esize() : 2;
@@ -1382,6 +1456,8 @@ fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *
     if (g->twin || g->orphan) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
     if (material_id >= 0 && material_id < (int)g->mats.size() && g->mats[material_id].yfmt)
         return fail(FDTDB_E_STATE, "the closure replaces a bath stored in 16 bits");
+    if (material_id >= 0 && material_id < (int)g->mats.size() && g->mats[material_id].bext())
+        return fail(FDTDB_E_STATE, "the closure replaces a thermal or anharmonic bath");
     if (material_id < 0 || material_id >= (int)g->mats.size() || g->mats[material_id].kind != K_BATH)
         return fail(FDTDB_E_INVALID, "the closure replaces the bath of a Lorentz-Bath material");
     if (width != kClosureWidth) return fail(FDTDB_E_INVALID, "closure width must be %d", kClosureWidth);
@@ -1656,6 +1732,7 @@ fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double *phase)
         for (auto &m : g->mats) {
             if (m.cw_dev) return fail(FDTDB_E_STATE, "learned closures are not available on Bloch grids");
             if (m.yfmt) return fail(FDTDB_E_STATE, "16-bit bath storage is not available on Bloch grids");
+            if (m.bext()) return fail(FDTDB_E_STATE, "thermal and anharmonic baths are not available on Bloch grids");
         }
     if (re->dfts.size() != im->dfts.size()) return fail(FDTDB_E_INVALID, "the parts need the same flux monitors");
     for (size_t i = 0; i < re->dfts.size(); i++) {

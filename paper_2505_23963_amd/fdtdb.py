@@ -66,6 +66,8 @@ SIGNATURES = [
                                     _dp, _dp, _dp]),
     ("fdtdb_set_bath_closure", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_float), C.c_int, _dp]),
     ("fdtdb_set_bath_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double]),
+    ("fdtdb_set_bath_thermal", C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_uint64]),
+    ("fdtdb_set_bath_anharmonic", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int]),
     ("fdtdb_get_closure_state", C.c_int, [C.c_void_p, C.c_int, C.c_int, _dp]),
     ("fdtdb_add_source", C.c_int, [C.c_void_p, C.c_int, C.POINTER(Box), C.c_double, C.c_double, C.c_double, _dp,
                                    C.POINTER(C.c_int)]),
@@ -293,6 +295,11 @@ class Grid:
                 if m.bath_storage is not None:
                     _check(L.fdtdb_set_bath_storage(h, mid.value, {"f16": 1, "bf16": 2}[m.bath_storage],
                                                     float(m.bath_scale)))
+                if getattr(m, "kT", 0.0):
+                    _check(L.fdtdb_set_bath_thermal(h, mid.value, float(m.kT), int(m.noise_seed)))
+                if getattr(m, "anharmonic", None) is not None:
+                    lam = np.ascontiguousarray(m.anharmonic, np.float64)
+                    _check(L.fdtdb_set_bath_anharmonic(h, mid.value, _ptr(lam), len(lam)))
             elif kind == "MultiPole":
                 nt = len(m.kinds)
                 kinds = (C.c_int * nt)(*[{"lorentz": 0, "drude": 1}[k] for k in m.kinds])

@@ -1,0 +1,178 @@
+"""Thermal (Langevin) and anharmonic (quartic) baths on the GPU against the oracle (fdtdb_set_bath_thermal,
+fdtdb_set_bath_anharmonic; the extensions named in the paper's outlook, Sec. V): FP64 state in 1D, 2D and
+3D (the general kernel and the component-split kernel; with an energy monitor, thermal only) at <= 1e-12,
+FP32 state on a crop of the large 3D layout with the benchmark's thermal set-up (the measure of
+tests/parity_util.py, <= 1e-5), checkpoint and resume of a thermal grid bit for bit (the noise depends only
+on seed, cell, step and component), and the refusals.  Each comparison also checks that the terms it
+covers are far above its tolerance (the run without them differs by much more)."""
+import numpy as np
+import pytest
+
+from fdtdb_inputs import configs
+from fdtdb_inputs.problem import (CLOSED, PERIODIC, PML, DftFlux, EnergyMonitor, LorentzBath, Problem, Source,
+                                  active_components, box)
+from tests.parity_util import TOL_F32, Lockstep
+
+pytestmark = pytest.mark.gpu
+
+
+def _bath(nb):
+    return np.linspace(0.85, 1.15, nb), np.full(nb, 0.02), np.full(nb, 0.06)
+
+
+def _problem(ndim, dtype, steps, kT=2e-4, lam=40.0, energy=False, seed=0x5EED):
+    if ndim == 1:
+        nb = 16
+        p = Problem(name="thermal1d", ndim=1, n=(500, 1, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(30, 0, 0),
+                    dtype=dtype, steps=steps)
+        xb = box((150, 260))
+        p.sources.append(Source(comp=2, box=box((100, 101)), omega_c=1.0, width=0.5))
+        p.dfts.append(DftFlux(0, box((330, 331)), np.linspace(0.6, 1.4, 33)))
+        if energy:
+            p.energies.append(EnergyMonitor(box((40, 460)), every=7))
+    elif ndim == 2:
+        nb = 8
+        p = Problem(name="thermal2d", ndim=2, n=(96, 80, 1), bc=(PML, PML, PERIODIC), pml_cells=(16, 16, 0),
+                    dtype=dtype, steps=steps)
+        xb = box((40, 70), (24, 60))
+        p.sources.append(Source(comp=2, box=box((28, 29), (20, 60)), omega_c=1.0, width=0.5))
+        p.dfts.append(DftFlux(0, box((78, 79), (16, 64)), np.linspace(0.6, 1.4, 17)))
+        if energy:
+            p.energies.append(EnergyMonitor(box((16, 80), (16, 64)), every=9))
+    else:
+        nb = 16
+        p = Problem(name="thermal3d", ndim=3, n=(8, 6, 120), bc=(PERIODIC, CLOSED, PML), pml_cells=(0, 0, 16),
+                    dtype=dtype, steps=steps)
+        xb = box((0, 8), (1, 5), (50, 80))
+        p.sources += [Source(comp=0, box=box((0, 8), (0, 6), (30, 31)), omega_c=1.0, width=0.5),
+                      Source(comp=2, box=box((3, 4), (2, 3), (35, 36)), omega_c=0.9, width=0.5, amplitude=0.4)]
+        p.dfts.append(DftFlux(2, box((0, 8), (0, 6), (95, 96)), np.linspace(0.6, 1.4, 9)))
+        if energy:
+            p.energies.append(EnergyMonitor(box((0, 8), (0, 6), (16, 104)), every=5))
+    wj, gj, kj = _bath(nb)
+    sig = np.random.default_rng(3).uniform(0.03, 0.08, int(np.prod([xb[1][a] - xb[0][a] for a in range(3)])))
+    p.materials.append(LorentzBath(xb, omega0=1.0, gamma0=0.01, eps_inf=1.5, sigma_cells=sig, n_bath=nb,
+                                   omega_j=wj, gamma_j=gj, k_j=kj, kT=kT, noise_seed=seed,
+                                   anharmonic=None if lam is None else np.full(nb, lam)))
+    return p
+
+
+def _compare_fp64(g, o, p, tol=1e-12):
+    e, h = active_components(p.ndim)
+    big = max(np.linalg.norm(o.field(c)) for c in list(e) + list(h))
+    worst = 0.0
+    for c in list(e) + list(h):
+        worst = max(worst, np.linalg.norm(g.field(c) - o.field(c)) / max(np.linalg.norm(o.field(c)), 1e-2 * big))
+    for c in e:
+        for lvl in (0, 1):
+            for get in ("polarization", "bath"):
+                ref = getattr(o, get)(0, c, lvl)
+                worst = max(worst, np.linalg.norm(getattr(g, get)(0, c, lvl) - ref) / max(np.linalg.norm(ref), 1e-30))
+    worst = max(worst, np.linalg.norm(g.flux(0) - o.flux(0)) / np.linalg.norm(o.flux(0)))
+    print(f"  worst relative error {worst:.2e}", flush=True)
+    assert worst < tol
+    return worst
+
+
+def _bath_state(x, p):
+    e, _ = active_components(p.ndim)
+    return np.concatenate([x.bath(0, c, 0).ravel() for c in e] + [x.polarization(0, c, 0) for c in e])
+
+
+@pytest.mark.parametrize("ndim,energy", [(1, False), (2, False), (3, False), (1, True), (3, True)])
+def test_thermal_anharmonic_fp64(oracle_lib, ndim, energy):
+    from paper_2505_23963_amd import Grid
+    steps = 700
+    lam = None if energy else 40.0          # an energy monitor over an anharmonic bath is refused
+    p = _problem(ndim, "f64", steps, lam=lam, energy=energy)
+    print(f"[gpu] {p.name} f64 {steps} steps, thermal{'' if energy else ' + anharmonic'}"
+          f"{' with energy monitor' if energy else ''}", flush=True)
+    g = Grid(p)
+    g.step(steps)
+    o = oracle_lib.run(p)
+    _compare_fp64(g, o, p)
+    if energy:
+        eg, eo = g.energy(0), o.energy(0)
+        assert eg.shape == eo.shape and np.max(np.abs(eg - eo)) < 1e-11 * np.abs(eo).max()
+    # the thermal and quartic terms are far above the tolerance
+    plain = Grid(_problem(ndim, "f64", steps, kT=0.0, lam=None, energy=energy))
+    plain.step(steps)
+    a, b = _bath_state(g, p), _bath_state(plain, p)
+    assert np.linalg.norm(a - b) > 1e-4 * np.linalg.norm(a)
+    if lam is not None:
+        harm = Grid(_problem(ndim, "f64", steps, lam=None))
+        harm.step(steps)
+        assert np.linalg.norm(a - _bath_state(harm, p)) > 1e-6 * np.linalg.norm(a)
+
+
+def test_thermal_anharmonic_fp32_large_layout_crop(oracle_lib):
+    """The large 3D layout (205-cell Lorentz-Bath slab, N_b = 16, component-split kernel) with the thermal and
+    anharmonic set-up the benchmark times, 16 x 16 x 512 crop, 1200 steps, FP32 state."""
+    from paper_2505_23963_amd import Grid
+    p = configs.config5_3d_large(nx=16, ny=16, steps=1200, nfreq=16)
+    configs.thermal_setup(p)
+    print(f"[gpu] thermal large-layout crop {p.n} f32, 1200 steps", flush=True)
+    g = Grid(p, dtype="f32")
+    o = oracle_lib.Oracle(p)
+    ls = Lockstep(g, o, p).run(1200, 400)
+    ls.report()
+    e, c = ls.worst()
+    assert e < TOL_F32 and c < TOL_F32, (e, c)
+
+
+def test_thermal_checkpoint_resumes_bitwise(tmp_path):
+    from paper_2505_23963_amd import Grid
+    p = _problem(1, "f32", 600)
+    a = Grid(p)
+    a.step(300)
+    path = str(tmp_path / "thermal.state")
+    a.save_state(path)
+    a.step(200)
+    b = Grid(p)
+    b.load_state(path)
+    b.step(200)
+    for comp in (2, 4):
+        assert np.array_equal(a.field(comp), b.field(comp))
+    assert np.array_equal(a.bath(0, 2, 0), b.bath(0, 2, 0))
+    # another seed is another set-up: its grid refuses the file
+    from paper_2505_23963_amd.fdtdb import E_STATE, FdtdbError
+    c = Grid(_problem(1, "f32", 600, seed=1))
+    with pytest.raises(FdtdbError) as err:
+        c.load_state(path)
+    assert err.value.status == E_STATE
+
+
+def test_thermal_refusals():
+    from paper_2505_23963_amd import Grid
+    from paper_2505_23963_amd.fdtdb import E_INVALID, E_STATE, FdtdbError, lib
+    L = lib()
+    g = Grid(_problem(1, "f32", 10, kT=0.0, lam=None))
+    mid = g.mat_ids[0]
+    assert L.fdtdb_set_bath_thermal(g.h, mid, -1.0, 1) == E_INVALID
+    assert L.fdtdb_set_bath_thermal(g.h, mid, float("nan"), 1) == E_INVALID
+    lam = np.ones(3)
+    assert L.fdtdb_set_bath_anharmonic(g.h, mid, lam.ctypes.data, 3) == E_INVALID     # 16 modes
+    assert L.fdtdb_set_bath_storage(g.h, mid, 1, 1024.0) == E_INVALID              # 1D: no 16-bit storage anyway
+    assert L.fdtdb_set_bath_thermal(g.h, mid, 1e-3, 1) == 0
+    g.step(1)
+    assert L.fdtdb_set_bath_thermal(g.h, mid, 1e-3, 1) == E_STATE
+    # 16-bit storage and a thermal bath exclude each other (either order)
+    q = configs.config5_3d_large(nx=4, ny=4, steps=1, nfreq=4)
+    q.materials[0].bath_storage = "f16"
+    q.materials[0].kT = 1e-6
+    with pytest.raises(FdtdbError) as err:
+        Grid(q)
+    assert err.value.status == E_STATE
+    # an energy monitor over an anharmonic bath (refused at the first step)
+    q = _problem(1, "f32", 1, energy=True)
+    with pytest.raises(FdtdbError) as err:
+        Grid(q).step(1)
+    assert err.value.status == E_STATE
+    # Bloch pairs
+    q = _problem(2, "f64", 1)
+    q.bc = (PML, PERIODIC, PERIODIC)
+    q.pml_cells = (16, 0, 0)
+    q.bloch = (0.0, 0.5, 0.0)
+    with pytest.raises(FdtdbError) as err:
+        Grid(q)
+    assert err.value.status == E_STATE
