@@ -517,6 +517,8 @@ class Batch:
                         wj, gj, kj = _arr(m.omega_j), _arr(m.gamma_j), _arr(m.k_j)
                     if m.sigma_cells is not None:
                         raise ValueError("batched cavities take a uniform sigma")
+                    if getattr(m, "kT", 0.0) or getattr(m, "anharmonic", None) is not None or m.bath_storage:
+                        raise ValueError("batched cavities take a harmonic bath at zero temperature in the state type")
                     _bcheck(L.fdtdb_batch_set_lorentz_bath(self.h, c, lo, hi, m.omega0, m.gamma0, m.eps_inf, m.sigma,
                                                            m.n_bath, _ptr(wj), _ptr(gj), _ptr(kj)))
                 else:

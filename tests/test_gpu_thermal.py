@@ -176,3 +176,13 @@ def test_thermal_refusals():
     with pytest.raises(FdtdbError) as err:
         Grid(q)
     assert err.value.status == E_STATE
+
+
+def test_batched_cavities_refuse_thermal_and_anharmonic_baths():
+    """The batched 1D launch carries neither term: a cavity that asks for one is refused, not run without it."""
+    from paper_2505_23963_amd import Batch
+    for field, value in (("kT", 1e-6), ("anharmonic", np.full(32, 1.0))):
+        cav = configs.config3_cavities(ncav=2, steps=10, nfreq=4)
+        setattr(cav[1].materials[1], field, value)
+        with pytest.raises(ValueError):
+            Batch(cav)
