@@ -241,7 +241,9 @@ struct BathCoef {
 //   with sa_j = (dt/2) k_j a_j / A and sb_j = (dt/2) k_j b_j / A;
 //   then, for a thermal or anharmonic bath, per mode j (stride kCoefExt): the noise amplitude per
 //   sqrt(sigma) dt^2 sqrt(2 g_j kT w0^2 / dt) / den_j, the quartic coefficient lambda_j dt^2 / den_j
-//   (den_j = 1 + g_j dt / 2), and the share (dt/2) k_j / A of the mode's extra term in the P update.
+//   (den_j = 1 + g_j dt / 2), and the share (dt/2) k_j / A of the mode's extra term in the P update;
+//   for a bath stored in 16 bits (scale s) instead, per mode: c_j s, sa_j / s, sb_j / s (the update of
+//   the scaled coordinates Y s).
 // Drude table: [0] dE = wp^2 dt^2 / (1 + g dt/2)  [1] dV = (1 - g dt/2)/(1 + g dt/2)  [2] rho = 1/wp^2.
 constexpr int kCoefHead = 8;
 constexpr int kCoefMode = 8;

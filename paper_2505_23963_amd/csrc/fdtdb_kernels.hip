@@ -941,18 +941,20 @@ __global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, c
 // ---------------------------------------------------------------------------------------------
 typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
 
+// the stored (scaled) coordinate u of a word, widened
 template <int YF>
-__device__ __forceinline__ double unpack16(nv4u w, int u, double inv_s) {
+__device__ __forceinline__ double unpack16(nv4u w, int u) {
     const unsigned bits = (u & 1) ? (w[u >> 1] >> 16) : (w[u >> 1] & 0xffffu);
     float f;
     if constexpr (YF == 1) f = (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
     else f = __builtin_bit_cast(float, bits << 16);
-    return (double)f * inv_s;
+    return (double)f;
 }
 
+// a scaled coordinate rounded to binary32 and then to the 16-bit format
 template <int YF>
-__device__ __forceinline__ unsigned pack16(double y, double s) {
-    const float f = (float)(y * s);
+__device__ __forceinline__ unsigned pack16(double y) {
+    const float f = (float)y;
     if constexpr (YF == 1) return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)f);
     unsigned x = __builtin_bit_cast(unsigned, f);
     x += 0x7fffu + ((x >> 16) & 1u);                 // round to nearest even on the dropped half
@@ -996,7 +998,8 @@ __device__ __forceinline__ void bath_component16(const EArgs &a, int t) {
     double amp[kMaxSources];
     load_amps(a, amp);
     const double sig = has_sig ? (double)sig_raw : a.sigma0;
-    const double inv_s = a.yinv, sc = a.yscale;
+    // the coordinates stay scaled (Y s): the bath force and the coupling to dP take the coefficients of the
+    // block after the modes (sa_j / s, sb_j / s and c_j s), the recurrence a_j, b_j + 1 as they are
     typedef const __attribute__((address_space(4))) double *cdp;
     cdp co = (cdp)a.coef;
     const double En = Eo + a.inv_eps * (a.dt * (t1 - t2) - (Pc - Pp)) - source_term(a, amp, C, i, j, k);
@@ -1004,10 +1007,10 @@ __device__ __forceinline__ void bath_component16(const EArgs &a, int t) {
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         asm volatile("" : "+s"(co));
-        const cdp md = co + kCoefHead + 8 * w * kCoefMode;
+        const cdp xs = co + kCoefHead + 4 * NG * kCoefMode + 8 * w * kCoefExt;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            S += md[u * kCoefMode + 3] * unpack16<YF>(yc[w], u, inv_s) + md[u * kCoefMode + 4] * unpack16<YF>(yp[w], u, inv_s);
+            S += xs[u * kCoefExt + 1] * unpack16<YF>(yc[w], u) + xs[u * kCoefExt + 2] * unpack16<YF>(yp[w], u);
     }
     asm volatile("" : "+s"(co));
     const double Pnew = co[0] * sig * En - co[1] * Pc - co[2] * Pp - S;
@@ -1018,12 +1021,12 @@ __device__ __forceinline__ void bath_component16(const EArgs &a, int t) {
     for (int w = 0; w < NW; ++w) {
         asm volatile("" : "+s"(co));
         const cdp md = co + kCoefHead + 8 * w * kCoefMode;
+        const cdp xs = co + kCoefHead + 4 * NG * kCoefMode + 8 * w * kCoefExt;
         unsigned h[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            h[u] = pack16<YF>(md[u * kCoefMode + 0] * unpack16<YF>(yc[w], u, inv_s) +
-                                  md[u * kCoefMode + 1] * unpack16<YF>(yp[w], u, inv_s) + md[u * kCoefMode + 2] * dP,
-                              sc);
+            h[u] = pack16<YF>(md[u * kCoefMode + 0] * unpack16<YF>(yc[w], u) +
+                              md[u * kCoefMode + 1] * unpack16<YF>(yp[w], u) + xs[u * kCoefExt + 0] * dP);
         nv4u o;
         o[0] = h[0] | (h[1] << 16);
         o[1] = h[2] | (h[3] << 16);

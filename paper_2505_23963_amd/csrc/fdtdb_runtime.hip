@@ -1363,7 +1363,8 @@ fdtdb_status fdtdb_set_lorentz_bath(fdtdb_grid g, const fdtdb_box *box, double o
     return FDTDB_OK;
 }
 
-// Extension block of the coefficient table of a thermal or anharmonic bath (layout with the table's)
+// Block of the coefficient table after the modes (layout with the table's): the thermal / anharmonic
+// terms, or for a bath stored in 16 bits the coefficients that act on scaled coordinates
 static fdtdb_status rebuild_ext(fdtdb_grid_s *g, Material &m) {
     const double dt = g->dt, w02 = m.omega0 * m.omega0;
     const size_t base = kCoefHead + (size_t)kCoefMode * 4 * m.ng;
@@ -1381,6 +1382,15 @@ static fdtdb_status rebuild_ext(fdtdb_grid_s *g, Material &m) {
             x[0] = m.kT > 0.0 ? dt * dt * std::sqrt(2.0 * m.gj[jb] * m.kT * w02 / dt) / den : 0.0;
             x[1] = m.lam.empty() ? 0.0 : m.lam[jb] * dt * dt / den;
             x[2] = 0.5 * dt * m.kj[jb] / A;
+        }
+    } else if (m.yfmt) {
+        m.coef.resize(base + (size_t)kCoefExt * 4 * m.ng, 0.0);
+        for (int jb = 0; jb < 4 * m.ng; jb++) {
+            const double *md = &m.coef[kCoefHead + (size_t)kCoefMode * jb];
+            double *x = &m.coef[base + (size_t)kCoefExt * jb];
+            x[0] = md[2] * m.yscale;
+            x[1] = md[3] / m.yscale;
+            x[2] = md[4] / m.yscale;
         }
     }
     void *old = m.coef_dev;
@@ -1446,7 +1456,7 @@ fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, d
         }
     m.yfmt = format;
     m.yscale = format == FDTDB_BATH_STATE ? 1.0 : scale;
-    return FDTDB_OK;
+    return rebuild_ext(g, m);
 }
 
 fdtdb_status fdtdb_set_bath_closure(fdtdb_grid g, int material_id, const float *weights, int width,
