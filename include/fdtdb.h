@@ -240,8 +240,9 @@ fdtdb_status fdtdb_set_bath_storage(fdtdb_grid g, int material_id, int format, d
  * pairs with its damping for the effective mass rho = 1 / (eps0 sigma omega0^2) of eq:H_full, so that
  * the matter relaxes to the Gibbs state at temperature kT (energy units, same as the fields').  Over
  * one step the force is sqrt(2 gamma kT / (rho dt)) xi with xi = sqrt(12) (u - 1/2), u = (x + 1/2) /
- * 2^32, x a 32-bit word of Philox4x32-10 with counter (linear cell index of the grid, step index n,
- * E component, variate / 4) and key (seed low word, seed high word), lane variate % 4; bath mode j
+ * 2^32, x a 32-bit word of Philox4x32-10 with counter (linear cell index of the grid, step index n
+ * modulo 2^32, E component, variate / 4) and key (seed low word, seed high word), lane variate % 4
+ * (a run longer than 2^32 steps repeats its noise); bath mode j
  * takes variate j and P variate N_b.  It enters eq:Yzj_finite_difference as + dt^2 eta_j /
  * (1 + gamma_j dt / 2) and, through the substituted Y_j^{n+1}, eq:Pz_update-LB (and P's own force as
  * + dt^2 eta_P in its bracket).  kT = 0 removes it.  The noise depends only on (seed, cell, step,
