@@ -18,7 +18,6 @@ constexpr int kBlock = 256;          // threads per block of the stencil kernels
 constexpr int kBathBlock = 128;
 constexpr unsigned kBathLdsReserve = 36 * 1024;
 constexpr int kDftSlots = 64;        // steps staged before a DFT flush
-constexpr int kDftFreqTile = 32;     // frequencies per thread in the DFT flush
 
 // Update kind of a region.
 enum Kind : int { K_BACKGROUND = 0, K_DRUDE = 1, K_BATH = 2, K_CLOSURE = 3, K_MULTI = 4 };

@@ -1629,43 +1629,68 @@ __global__ void k_dft_twiddle(const Clock *clk, const double *omega, int nf, int
 }
 
 // acc[field][f][p] += sum_b stage[b][field][p] * tw[b][f]
+// One thread per (plane point, field): its staged samples are read once and held in registers, and
+// the frequencies are swept in chunks whose twiddles sit in LDS (register tiles of kFlushTile
+// frequencies, whose accumulators are loaded before their sums are formed, so that the loads overlap
+// the arithmetic).  Each accumulator is read and written once per flush, and each sum runs over the
+// slots in order, as a plain loop would.  (Before: one launch dimension per 32-frequency tile, the samples
+// read again for every tile: 12.9 GB moved per flush of the 512^2 plane against 9.1 GB; 3.75 ms per flush
+// then, 3.74 ms with the samples read once, 2.90 ms with the accumulator loads issued ahead, 2.83 ms with
+// 64-frequency chunks; 4-frequency register tiles 2.92 ms.)
+constexpr int kFlushChunk = 64;      // frequencies whose twiddles are in LDS at once (64 KB)
+constexpr int kFlushTile = 8;        // frequencies accumulated in registers at once
 __global__ __launch_bounds__(kBlock) void k_dft_flush(const double *stage, const double *tw, int npts, int nf,
                                                      int nslots, double2 *acc) {
-    __shared__ double2 ltw[kDftSlots][kDftFreqTile];
+    __shared__ double2 ltw[kDftSlots][kFlushChunk];
     const int field = blockIdx.y;
-    const int f0 = blockIdx.z * kDftFreqTile;
     const int hsel = field >= 2 ? 2 : 0;
-    for (int id = threadIdx.x; id < nslots * kDftFreqTile; id += kBlock) {
-        const int b = id / kDftFreqTile, f = id - b * kDftFreqTile;
-        double2 v = make_double2(0.0, 0.0);
-        if (f0 + f < nf) {
-            const double *o = tw + 4 * ((long long)b * nf + f0 + f);
-            v = make_double2(o[hsel], o[hsel + 1]);
-        }
-        ltw[b][f] = v;
-    }
-    __syncthreads();
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= npts) return;
-    double re[kDftFreqTile], im[kDftFreqTile];
+    const bool live = p < npts;
+    double x[kDftSlots];
 #pragma unroll
-    for (int f = 0; f < kDftFreqTile; ++f) { re[f] = 0.0; im[f] = 0.0; }
-    for (int b = 0; b < nslots; ++b) {
-        const double x = stage[((long long)b * 4 + field) * npts + p];
-#pragma unroll
-        for (int f = 0; f < kDftFreqTile; ++f) {
-            re[f] += x * ltw[b][f].x;
-            im[f] += x * ltw[b][f].y;
+    for (int b = 0; b < kDftSlots; ++b)
+        x[b] = (live && b < nslots) ? __builtin_nontemporal_load(stage + ((long long)b * 4 + field) * npts + p) : 0.0;
+    for (int c0 = 0; c0 < nf; c0 += kFlushChunk) {
+        __syncthreads();                             // the previous chunk's twiddles are read by now
+        for (int id = threadIdx.x; id < nslots * kFlushChunk; id += kBlock) {
+            const int b = id / kFlushChunk, f = id - b * kFlushChunk;
+            double2 v = make_double2(0.0, 0.0);
+            if (c0 + f < nf) {
+                const double *o = tw + 4 * ((long long)b * nf + c0 + f);
+                v = make_double2(o[hsel], o[hsel + 1]);
+            }
+            ltw[b][f] = v;
         }
-    }
+        __syncthreads();
+        if (!live) continue;
+        for (int t0 = 0; t0 < kFlushChunk && c0 + t0 < nf; t0 += kFlushTile) {
+            double re[kFlushTile], im[kFlushTile];
+            double2 av[kFlushTile];
 #pragma unroll
-    for (int f = 0; f < kDftFreqTile; ++f) {
-        if (f0 + f >= nf) continue;
-        double2 *d = acc + ((long long)field * nf + f0 + f) * npts + p;
-        double2 v = *d;
-        v.x += re[f];
-        v.y += im[f];
-        *d = v;
+            for (int f = 0; f < kFlushTile; ++f) {
+                re[f] = 0.0; im[f] = 0.0;
+                av[f] = c0 + t0 + f < nf ? acc[((long long)field * nf + c0 + t0 + f) * npts + p] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int b = 0; b < kDftSlots; ++b) {
+                if (b < nslots) {
+#pragma unroll
+                    for (int f = 0; f < kFlushTile; ++f) {
+                        re[f] += x[b] * ltw[b][t0 + f].x;
+                        im[f] += x[b] * ltw[b][t0 + f].y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < kFlushTile; ++f) {
+                if (c0 + t0 + f >= nf) continue;
+                double2 *d = acc + ((long long)field * nf + c0 + t0 + f) * npts + p;
+                double2 v = av[f];
+                v.x += re[f];
+                v.y += im[f];
+                *d = v;
+            }
+        }
     }
 }
 
@@ -1913,8 +1938,7 @@ hipError_t launch_dft_flush(const Clock *clk, const double *omega, int nf, int n
                             const double *stage, int npts, double2 *acc, hipStream_t s) {
     const int ntw = nf * nslots;
     hipLaunchKernelGGL(k_dft_twiddle, dim3((ntw + 255) / 256), dim3(256), 0, s, clk, omega, nf, nslots, dt, tw);
-    hipLaunchKernelGGL(k_dft_flush, dim3(nblocks(npts), 4, (nf + kDftFreqTile - 1) / kDftFreqTile), dim3(kBlock), 0, s,
-                       stage, tw, npts, nf, nslots, acc);
+    hipLaunchKernelGGL(k_dft_flush, dim3(nblocks(npts), 4), dim3(kBlock), 0, s, stage, tw, npts, nf, nslots, acc);
     return hipGetLastError();
 }
 
