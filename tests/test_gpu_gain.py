@@ -2,7 +2,7 @@
 
 A closure is trained on the GPU from explicit N_b = 64 Lorentzian-bath trajectories (recorded on
 a 256^2 grid), then a 512^2 run of the same material is compared with the explicit bath (the
-judge) over 1500 steps, shorter than the discrete bath's revival time 2 pi / dw (about 1980
+reference) over 1500 steps, shorter than the discrete bath's revival time 2 pi / dw (about 1980
 steps), which a 4-state closure cannot follow.  Compared: (i) the learned closure, (ii) the plain
 Lorentz model with gamma = gamma0 + dephasing (the method without a bath), (iii) an explicit
 bath of 2 modes (Table 1 rule; 16 bytes more state per cell than K = 4 floats' 16).
