@@ -162,3 +162,45 @@ def test_fp32_config2_full_size_200_steps():
         assert err < TOL_F32, (name, err)
     full = np.array([np.linalg.norm(g.field(c)) for c in range(6)])
     assert np.max(np.abs(full - ref["field_norms"]) / ref["field_norms"].max()) < TOL_F32
+
+
+def test_fp32_config5_full_size_mirror_symmetry():
+    """The large 3D layout at its full 512^3 size, in the launch configuration the benchmark times, checked by
+    a property that holds at any size: the set-up (periodic x and y, a plane E_x current with a Gaussian
+    profile centred between rows ny/2 - 1 and ny/2, materials uniform in x and y) is symmetric under the mirror
+    y -> (ny - 1) - y, so after 360 steps (the pulse inside the Lorentz-Bath slab) E_x, E_z, H_y and P_x, P_z
+    are even and E_y, H_x, H_z, P_y and the bath of E_y odd under it (a component staggered by half a cell
+    along y maps row j to ny - 2 - j).  The updates are mirror images of each other operation by operation,
+    so the fields match to rounding (bar 1e-6 of each field's largest value).  Indexing faults that show only
+    at full size (block order, 32-bit offsets, region cuts of the 512^2 planes) break the symmetry."""
+    import torch
+    from paper_2505_23963_amd import Grid
+    p = configs.config5_3d_large(steps=360, nfreq=8)
+    n = p.n[1]
+    print(f"[gpu] config5 full size {p.n} f32, 360 steps, mirror symmetry", flush=True)
+    g = Grid(p)
+    g.step(360)
+    g.synchronize()
+    rows = {False: torch.arange(n - 1, -1, -1), True: (n - 2 - torch.arange(n)) % n}
+    # component: (sign under the mirror, staggered along y)
+    parity = {0: (1, False), 1: (-1, True), 2: (1, False), 3: (-1, True), 4: (1, False), 5: (-1, True)}
+    t = torch.empty(p.cells, dtype=torch.float64, device="cuda")
+    for c, (sgn, half) in parity.items():
+        g.field_into(c, t.data_ptr())
+        torch.cuda.synchronize()
+        f = t.view(p.n)
+        err = (f - sgn * f[:, rows[half].cuda(), :]).abs().max().item()
+        scale = f.abs().max().item()
+        print(f"  field {c}: max {scale:.3e}, mirror mismatch {err:.3e}", flush=True)
+        assert scale > 0 and err <= 1e-6 * scale, (c, err, scale)
+    del t
+    nz = p.materials[0].box[1][2] - p.materials[0].box[0][2]
+    for c, sgn in ((0, 1), (1, -1), (2, 1)):         # P and the bath sit where their E component does
+        P = g.polarization(0, c, 0).reshape(n, n, nz)
+        err = np.max(np.abs(P - sgn * P[:, rows[c == 1].numpy(), :]))
+        print(f"  P{c}: max {np.abs(P).max():.3e}, mirror mismatch {err:.3e}", flush=True)
+        assert np.abs(P).max() > 0 and err <= 1e-6 * np.abs(P).max(), (c, err)
+    Y = g.bath(0, 1, 0).reshape(-1, n, n, nz)
+    err = np.max(np.abs(Y + Y[:, :, rows[True].numpy(), :]))
+    print(f"  bath of E_y: max {np.abs(Y).max():.3e}, mirror mismatch {err:.3e}", flush=True)
+    assert np.abs(Y).max() > 0 and err <= 1e-6 * np.abs(Y).max()
