@@ -240,3 +240,49 @@ def test_fp32_config5_full_size_20_steps_sampled_columns(oracle_lib):
             worst[name] = max(np.linalg.norm(got[i] - want[i]) / scale for i in range(3))
             assert np.linalg.norm(got - want) / scale <= 1e-5 and worst[name] <= 1e-5, (x0, y0, name, worst[name])
         print(f"  column ({x0}, {y0}): worst component E {worst['E']:.2e}, H {worst['H']:.2e}", flush=True)
+
+
+def test_fp32_config4_full_size_100_steps_sampled_blocks(oracle_lib):
+    """The 2D workload at its full 2048^2 size (CPML on every side, the N_b = 64 patch) for 100 steps against
+    the oracle on sampled 21 x 21 blocks.  After 100 steps a cell depends on nothing farther than 200 cells,
+    so the oracle runs a window of the grid that keeps the full grid's own boundary (its CPML and the source
+    line's end) on the sides the block is near and puts its other sides, with their own CPML, more than 200
+    cells away.  Blocks by the source line, at its lower end in the corner, and at its upper end.  E_z and
+    (H_x, H_y) against their vector fields' norm on the block (reading R11), <= 1e-5."""
+    from fdtdb_inputs.problem import PML, PERIODIC, Problem, box
+    from paper_2505_23963_amd import Grid
+    steps, reach, half = 100, 240, 10
+    full = configs.config4_2d(steps=steps, nfreq=4)
+    n = full.n[0]
+    src = full.sources[0]
+    print(f"[gpu] config4 full size {full.n} f32, {steps} steps, sampled blocks", flush=True)
+    g = Grid(full)
+    g.step(steps)
+    g.synchronize()
+    fields = {c: g.field(c)[:, :, 0] for c in (2, 3, 4)}
+    for x0, y0 in ((60, 1024), (40, 40), (100, 2010)):
+        xlo, xhi = 0, x0 + reach                                  # the left boundary is the grid's own
+        ylo = 0 if y0 - reach < 0 else y0 - reach
+        yhi = n if y0 + reach > n else y0 + reach
+        assert xhi <= full.materials[0].box[0][0]                 # the window holds no bath cells
+        w = Problem(name="window", ndim=2, n=(xhi - xlo, yhi - ylo, 1), bc=(PML, PML, PERIODIC),
+                    pml_cells=(32, 32, 0), dtype="f64", steps=steps)
+        # the source line clipped to the window (its ends are the grid's own where the window reaches them)
+        s_lo = max(src.box[0][1], ylo) - ylo
+        s_hi = min(src.box[1][1], yhi) - ylo
+        w.sources.append(configs.gaussian_pulse(2, box((src.box[0][0], src.box[1][0]), (s_lo, s_hi)),
+                                                omega_c=src.omega_c, width=src.width))
+        o = oracle_lib.Oracle(w)
+        o.step(steps)
+        bx = slice(x0 - half - xlo, x0 + half + 1 - xlo)
+        by = slice(y0 - half - ylo, y0 + half + 1 - ylo)
+        gx, gy = slice(x0 - half, x0 + half + 1), slice(y0 - half, y0 + half + 1)
+        res = {}
+        for name, comps in (("E", (2,)), ("H", (3, 4))):
+            want = np.stack([o.field(c)[bx, by, 0] for c in comps])
+            got = np.stack([fields[c][gx, gy] for c in comps])
+            scale = np.linalg.norm(want)
+            assert scale > 0, (x0, y0, name)
+            res[name] = np.linalg.norm(got - want) / scale
+            assert res[name] <= 1e-5, (x0, y0, name, res[name])
+        print(f"  block at ({x0}, {y0}): E {res['E']:.2e}, H {res['H']:.2e}", flush=True)
