@@ -273,7 +273,8 @@ fdtdb_status fdtdb_step(fdtdb_grid g, int64_t nsteps);
 /* Wait for the grid's stream and run the watchdog: E_DIVERGED when a field holds a non-finite
  * value, or when the total of an energy monitor over every cell outside the CPML layers, sampled
  * after every source has ended (t > 2 t0), exceeds twice its smallest value since then while above
- * 1 % of its value when the sources ended (a passive grid's exact discrete energy cannot grow);
+ * 1 % of its value when the sources ended (a passive grid's exact discrete energy cannot grow; the
+ * energy check is off on grids with a thermal bath, which feeds energy in, and on Bloch pairs);
  * E_DEVICE on an asynchronous device error. */
 fdtdb_status fdtdb_synchronize(fdtdb_grid g);
 

@@ -1780,6 +1780,8 @@ fdtdb_status fdtdb_steps_done(fdtdb_grid g, int64_t *steps) {
 // field overflows.
 fdtdb_status energy_watchdog(fdtdb_grid_s *g) {
     if (g->twin || g->orphan) return FDTDB_OK;   // a Bloch pair conserves the sum over both parts only
+    for (auto &m : g->mats)                      // a thermal bath feeds energy in: the grid is not passive
+        if (m.kT > 0.0) return FDTDB_OK;
     double t_off = 0.0;
     for (auto &x : g->srcs) t_off = std::max(t_off, 10.0 / x.width);
     for (auto &e : g->ens) {

@@ -218,3 +218,22 @@ def test_thermal_grid_reaches_equipartition():
     print(f"  bath modes {ey.min():.3f}-{ey.max():.3f} (mean {ey.mean():.3f}), P {ep:.3f}", flush=True)
     assert abs(ey.mean() - 1) < 0.03 and np.max(np.abs(ey - 1)) < 0.06
     assert abs(ep - 1) < 0.06
+
+
+def test_thermal_grid_heating_does_not_trip_the_energy_watchdog():
+    """A thermal grid started at rest with a whole-grid energy monitor heats up (its energy grows from zero);
+    the energy-growth watchdog, made for passive grids, must not call that a divergence.  The non-finite
+    check still runs."""
+    from paper_2505_23963_amd import Grid
+    n = 200
+    p = Problem(name="thermal-watchdog", ndim=1, n=(n, 1, 1), bc=(PERIODIC, PERIODIC, PERIODIC), dtype="f32",
+                steps=0)
+    wj, gj, kj = _bath(4)
+    p.materials.append(LorentzBath(box((0, n)), omega0=0.3, gamma0=0.02, eps_inf=1.0, sigma=0.05, n_bath=4,
+                                   omega_j=wj * 0.3, gamma_j=gj, k_j=kj * 0.5, kT=1e-4, noise_seed=5))
+    p.energies.append(EnergyMonitor(box((0, n)), every=10))
+    g = Grid(p)
+    g.step(3000)
+    g.synchronize()                      # raises E_DIVERGED if the watchdog took the heating for growth
+    e = g.energy(0).sum(axis=1)
+    assert e[0] == 0.0 and e[-1] > 0.0
