@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gcell-updates/s & % HBM roofline; learned vs explicit bath at <=1e-3 error"
 HBM_PEAK_GBS = 8000.0
-KIND = {0: "background", 1: "drude", 2: "lorentz_bath", 3: "closure"}
+KIND = {0: "background", 1: "drude", 2: "lorentz_bath", 3: "closure", 4: "multi_term"}
 
 
 # the functions each counted kernel consists of (its own code and the helpers it calls)
@@ -610,6 +610,70 @@ def bench_planar3d(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_variants(args):
+    """The method's variants timed at full size: (i) the 512^3 layout with its slab a sum of three terms
+    (Lorentz, Lorentz, Drude; Sec. II.A) on the general kernel; (ii) a 2048 x 1024 2D grid (CPML along x,
+    N_b = 64 Lorentzian-form patch over all of y) Bloch-periodic along y with phase 0.8, against the same grid
+    plain periodic.  Gcell-updates/s (a complex cell counted once) and the dominant launch against its
+    algorithmic bytes (events around every launch, in a separate profiled run)."""
+    import numpy as np
+    import torch
+    from fdtdb_inputs import configs
+    from fdtdb_inputs.problem import PML, PERIODIC, LorentzBath, MultiPole, Problem, Source, box
+    from paper_2505_23963_amd import Grid
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    warmup, steps = _whole_periods(args.warmup), _whole_periods(args.steps)
+
+    def run(p):
+        g = Grid(p, stream=stream.cuda_stream)
+        g.step(warmup)
+        g.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.set_profiling(True)
+        g.kernel_records()
+        g.step(16)
+        g.synchronize()
+        recs = [r for r in g.kernel_records() if r["launches"]]
+        dom = max(recs, key=lambda r: r["ms_total"] / r["launches"])
+        ms = dom["ms_total"] / dom["launches"]
+        del g
+        return {"value": round(p.cells * steps / dt / 1e9, 4), "ms_per_step": round(dt / steps * 1e3, 4),
+                "dominant_kernel": KIND[dom["kind"]], "kernel_ms": round(ms, 4), "kernel_bytes": dom["bytes"],
+                "kernel_frac_of_hbm_peak": round(dom["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {"metric": METRIC, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic"}
+    p = configs.config5_3d_large(steps=0, nfreq=16)
+    slab = p.materials[0]
+    p.materials[0] = MultiPole(slab.box, eps_inf=1.0, kinds=("lorentz", "lorentz", "drude"), omega=(1.0, 1.2, 0.5),
+                               gamma=(0.01, 0.02, 0.01), sigma=(0.05, 0.02, 0.0))
+    print(f"[bench] 512^3 with a three-term slab: warm-up {warmup}, timed {steps} steps", file=sys.stderr, flush=True)
+    out["multi_term_512cubed"] = run(p)
+
+    def bloch2d(phase):
+        nx, ny, nb = 2048, 1024, 64
+        q = Problem(name="bloch2d", ndim=2, n=(nx, ny, 1), bc=(PML, PERIODIC, PERIODIC), pml_cells=(32, 0, 0),
+                    dtype="f32", steps=0, bloch=None if phase is None else (0.0, phase, 0.0))
+        q.materials.append(LorentzBath(box((512, 1536), (0, ny)), omega0=1.0, gamma0=0.001, eps_inf=1.0, sigma=0.05,
+                                       n_bath=nb, form="lorentzian", width=0.4, bath_gamma=0.4 / (nb - 1) / 2,
+                                       dephasing=0.02))
+        y = np.arange(ny)
+        k = (phase or 0.0) / ny
+        q.sources.append(Source(comp=2, box=box((48, 49), (0, ny)), omega_c=1.0, width=0.5, profile=np.cos(k * y),
+                                profile_im=None if phase is None else np.sin(k * y)))
+        return q
+    print("[bench] 2D Bloch grid and its plain twin", file=sys.stderr, flush=True)
+    out["bloch_2d_2048x1024"] = run(bloch2d(0.8))
+    out["periodic_2d_2048x1024"] = run(bloch2d(None))
+    out["bloch_over_periodic"] = round(out["bloch_2d_2048x1024"]["value"] / out["periodic_2d_2048x1024"]["value"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -629,10 +693,12 @@ def main():
                     help="write profiles/traffic_counters.json from rocprofv3 counter runs under this folder")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--workload", choices=["large3d", "planar3d", "cavities", "closure2d", "fp1d"], default="large3d",
+    ap.add_argument("--workload", choices=["large3d", "planar3d", "cavities", "closure2d", "fp1d", "variants"],
+                    default="large3d",
                     help="large3d: the 512^3 line (default); planar3d: the 256x256x512 planar cavity; cavities: the "
                          "64-cavity batched 1D workload; closure2d: learned closure vs explicit bath on the 2D 2048^2 "
-                         "grid; fp1d: the 1D Fabry-Perot workload in FP64")
+                         "grid; fp1d: the 1D Fabry-Perot workload in FP64; variants: a three-term slab on the "
+                         "512^3 layout and a Bloch-periodic 2D grid against its plain twin")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: fdtdb runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -646,7 +712,7 @@ def main():
         traffic_from_rocprof(args.traffic_from)
         return
     {"large3d": bench_large3d, "planar3d": bench_planar3d, "cavities": bench_cavities, "closure2d": bench_closure2d,
-     "fp1d": bench_fp1d}[args.workload](args)
+     "fp1d": bench_fp1d, "variants": bench_variants}[args.workload](args)
 
 
 if __name__ == "__main__":

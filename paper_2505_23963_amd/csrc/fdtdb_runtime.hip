@@ -108,6 +108,9 @@ struct Region {
     void *psiE[3][2] = {};
     void *psiH[3][2] = {};
     bool energy = false;
+    // on a Bloch pair: the region reads the other part (E: the first row along a Bloch axis, whose lower
+    // neighbour wraps; H: the last row, whose upper neighbour wraps) and takes the generic kernels
+    bool wrap = false;
     long long block_base = 0;
     // H only: z-term psi for z < zlo and z >= zhi alone, in zw = (zlo - lo) + (hi - zhi) slots per
     // row; zw = 0: per cell of the region
@@ -364,6 +367,7 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 br[a].push_back((int)m.lo[a]);
                 br[a].push_back((int)m.hi[a]);
             }
+        if (g->twin && a < g->ndim && g->bph[a] != 0.0) br[a].push_back(h ? (int)g->n[a] - 1 : 1);
         std::sort(br[a].begin(), br[a].end());
         br[a].erase(std::unique(br[a].begin(), br[a].end()), br[a].end());
     }
@@ -386,6 +390,8 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 int mask = 0;
                 for (int a = 0; a < g->ndim; a++)
                     if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= up[a])) mask |= 1 << a;
+                for (int a = 0; g->twin && a < g->ndim; a++)     // bit 8: a row that reads across a Bloch axis
+                    if (g->bph[a] != 0.0 && lo[a] == (h ? g->n[a] - 1 : 0)) mask |= 1 << 8;
                 auto k = std::make_pair(mat, mask);
                 if (!ids.count(k)) {
                     int id = (int)ids.size();
@@ -427,7 +433,8 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 r.lo[1] = br[1][y]; r.hi[1] = br[1][y1];
                 r.lo[2] = br[2][z]; r.hi[2] = br[2][z1];
                 r.mat = rev[id].first;
-                r.pml_mask = rev[id].second;
+                r.pml_mask = rev[id].second & 0xff;
+                r.wrap = (rev[id].second >> 8) & 1;
                 r.eps = r.mat >= 0 ? g->mats[r.mat].eps : 1.0;
                 out.push_back(r);
             }
@@ -490,7 +497,8 @@ void region_bytes(const fdtdb_grid_s *g, const Region &r, double *be, double *bh
         if (m.kind == K_DRUDE) e += 2.0 * ne * w;
         else if (m.kind == K_BATH) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 3.0 * ne * m.nb * (m.yfmt ? 2.0 : w);
         else if (m.kind == K_CLOSURE) e += 3.0 * ne * w + (m.sigma_per_cell ? w : 0.0) + 2.0 * ne * 16.0;
-        else if (m.kind == K_MULTI) e += 3.0 * ne * m.nterm * w;
+        else if (m.kind == K_MULTI)      // a Lorentz term reads two levels and writes one, a Drude term its increment
+            for (int t = 0; t < m.nterm; t++) e += (m.coef[kCoefHead + kCoefMode * t + 5] != 0.0 ? 2.0 : 3.0) * ne * w;
     }
     *be = e;
     *bh = h;
@@ -595,8 +603,8 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
             if (rg.mat >= 0) {
                 const Material &mt = g->mats[rg.mat];
                 const bool m4 = mt.mext[2] % 4 == 0 && (rg.lo[2] - (int)mt.lo[2]) % 4 == 0;
-                (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy && !g->twin ? drude4 : solo).push_back(i);
-            } else if ((z4(rg) || bg_unaligned4(rg)) && !rg.energy && !g->twin) {   // Bloch pairs: generic kernels
+                (g->ndim == 3 && mt.kind == K_DRUDE && z4(rg) && m4 && !rg.energy && !rg.wrap ? drude4 : solo).push_back(i);
+            } else if ((z4(rg) || bg_unaligned4(rg)) && !rg.energy && !rg.wrap) {   // wrap rows: generic kernels
                 bg4.push_back(i);
             } else {
                 bg.push_back(i);
@@ -610,7 +618,7 @@ fdtdb_status finalize(fdtdb_grid_s *g) {
         for (int i = 0; i < (int)g->hregions.size(); i++) {
             if (g->hregions[i].zw && !z4(g->hregions[i]))   // per-row psi slots: vector kernel only
                 return fail(FDTDB_E_STATE, "H region with per-row psi slots but no 4-aligned z range");
-            (z4(g->hregions[i]) && !g->twin ? h4 : hg).push_back(i);
+            (z4(g->hregions[i]) && !g->hregions[i].wrap ? h4 : hg).push_back(i);
         }
         make(g->hlaunch, g->hregions, h4, true, true);
         make(g->hlaunch, g->hregions, hg, hg.size() > 1, false);
@@ -760,7 +768,9 @@ fdtdb_status enqueue_e(fdtdb_grid_s *g) {
         const Region &r = g->regions[L.regs[0]];
         EArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
-        if (g->twin) {
+        bool wrap = false;
+        for (int ri : L.regs) wrap |= g->regions[ri].wrap;
+        if (g->twin && wrap) {              // only launches over wrap rows read the other part
             a.bloch = 1;
             for (int c = 0; c < 3; c++) a.Htw[c] = g->twin->H[c];
             bloch_coefs(g, a.bcos, a.bsin);
@@ -867,7 +877,9 @@ fdtdb_status enqueue_h(fdtdb_grid_s *g) {
         const Region &r = g->hregions[L.regs[0]];
         HArgs a{};
         for (int c = 0; c < 3; c++) { a.E[c] = g->E[c]; a.H[c] = g->H[c]; }
-        if (g->twin) {
+        bool wrap = false;
+        for (int ri : L.regs) wrap |= g->hregions[ri].wrap;
+        if (g->twin && wrap) {
             for (int c = 0; c < 3; c++) a.Etw[c] = g->twin->E[c];
             bloch_coefs(g, a.bcos, a.bsin);
         }
