@@ -314,8 +314,10 @@ fdtdb_status fdtdb_energy(fdtdb_grid g, int monitor_id, double *out, int64_t cap
 /* Copy a field component (0..5 = Ex, Ey, Ez, Hx, Hy, Hz; zeros for a component the grid does not
  * carry), widened to FP64, into dst: n[0]*n[1]*n[2] doubles in C order.  dst_is_device = 0: dst
  * is host memory; otherwise dst is device memory on the grid's device (the copy runs on the grid's
- * stream; no host round trip).  The call synchronizes the grid's stream before and after the
- * copy.  E_INVALID for a null dst or a bad component. */
+ * stream; no host round trip).  The call synchronizes the grid's stream before the copy, the whole
+ * device before a write to a device destination (work another stream still has pending on dst, such
+ * as the fill of a freshly made buffer, finishes first), and the grid's stream after it.  E_INVALID for
+ * a null dst or a bad component. */
 fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, void *dst, int dst_is_device);
 
 /* Overwrite a field component from n[0]*n[1]*n[2] host doubles (rounded to the storage type). */
@@ -440,7 +442,7 @@ const char *fdtdb_batch_last_error(void);
 fdtdb_status fdtdb_add_probe(fdtdb_grid g, int material_id, int component, int n, const int64_t *cells,
                              int64_t nsteps, int *probe_id);
 /* Copy the record out (synchronizes): E and P are [nsteps][n] floats, host buffers, or device
- * buffers when to_device != 0. */
+ * buffers when to_device != 0 (written after the whole device has finished its pending work). */
 fdtdb_status fdtdb_probe_data(fdtdb_grid g, int probe_id, float *E, float *P, int to_device);
 
 /* Closure trainer (the network of fdtdb_set_bath_closure).  The target along each recorded
@@ -466,7 +468,8 @@ typedef struct {
 
 fdtdb_status fdtdb_trainer_create(const fdtdb_trainer_desc *desc, fdtdb_trainer *out);
 fdtdb_status fdtdb_trainer_destroy(fdtdb_trainer t);
-/* E, P: [nsteps][ntraj] floats as written by the recorder (host, or device if on_device != 0);
+/* E, P: [nsteps][ntraj] floats as written by the recorder (host, or device if on_device != 0; device
+ * sources are read after the whole device has finished its pending work, on any stream);
  * copied.  Computes the FP64 targets, the scales and the packed inputs. */
 fdtdb_status fdtdb_trainer_load(fdtdb_trainer t, const float *E, const float *P, int on_device);
 /* s_E, s_P, s_V, s_S (4 doubles, host). */

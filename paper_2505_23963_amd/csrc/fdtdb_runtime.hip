@@ -1665,6 +1665,7 @@ fdtdb_status fdtdb_probe_data(fdtdb_grid g, int probe_id, float *E, float *P, in
     const Probe &p = g->probes[probe_id];
     const size_t bytes = 4 * (size_t)p.n * (size_t)p.capacity;
     const hipMemcpyKind k = to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (to_device) HIP_TRY(hipDeviceSynchronize());   // work another stream has pending on E, P finishes first
     HIP_TRY(hipMemcpy(E, p.E, bytes, k));
     HIP_TRY(hipMemcpy(P, p.P, bytes, k));
     return FDTDB_OK;
@@ -1889,6 +1890,9 @@ fdtdb_status fdtdb_get_field(fdtdb_grid g, int component, void *dst, int dst_is_
     TRY(sync(g));
     const void *src = component < 3 ? g->E[component] : g->H[component - 3];
     if (!dst_is_device) return read_state(g, src, g->ncell, static_cast<double *>(dst));
+    // the destination may still have work pending on another stream (a caller's fill of a fresh buffer):
+    // wait for the whole device, so that this copy is the last write
+    HIP_TRY(hipDeviceSynchronize());
     double *out = static_cast<double *>(dst);
     if (!src) HIP_TRY(hipMemsetAsync(out, 0, 8 * (size_t)g->ncell, g->stream));
     else if (g->f64) HIP_TRY(hipMemcpyAsync(out, src, 8 * (size_t)g->ncell, hipMemcpyDeviceToDevice, g->stream));

@@ -664,6 +664,7 @@ fdtdb_status fdtdb_trainer_load(fdtdb_trainer t, const float *E, const float *P,
     const long long N = t->N, T = t->T;
     const size_t bytes = 4 * (size_t)(N * T);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (on_device) THIP(hipDeviceSynchronize());   // the caller's writes to E and P, on any stream, come first
     THIP(hipMemcpyAsync(t->Erec, E, bytes, kind, t->stream));
     THIP(hipMemcpyAsync(t->Prec, P, bytes, kind, t->stream));
     for (int j0 = 0; j0 < t->nb; j0 += 8) {
