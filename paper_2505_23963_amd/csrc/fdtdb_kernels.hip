@@ -932,6 +932,63 @@ __global__ __launch_bounds__(kBathBlock) void k_update_e_bath_c(const EArgs a, c
 }
 
 // ---------------------------------------------------------------------------------------------
+// Sum of Lorentz and Drude terms (Sec. II.A) in 3D, one (component, cell) per thread as for the bath:
+// E sees the sum of the terms' increments, a Lorentz term advances by its three-level update and a Drude
+// term by its increment's (coefficients per term in the table; the same arithmetic, in the same order,
+// as the general kernel).  Real grids without CPML terms or energy sampling.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int C>
+__device__ __forceinline__ void multi_component(const EArgs &a, int t) {
+    int i, j, k;
+    unflatten<3>(t, a.lo, a.ext, a.ext12, i, j, k);
+    const int s0 = a.n[1] * a.n[2], s1 = a.n[2];
+    const int q = i * s0 + j * s1 + k;
+    const int coord[3] = {i, j, k};
+    const int stride[3] = {s0, s1, 1};
+    const int m = ((i - a.mlo[0]) * a.mext[1] + (j - a.mlo[1])) * a.mext[2] + (k - a.mlo[2]);
+    constexpr int a1 = curl_a1(C), a2 = curl_a2(C);
+    const double t1 = ldd<T>(a.H[a2], q) - at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]);
+    const double t2 = ldd<T>(a.H[a1], q) - at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]);
+    T *Ec = static_cast<T *>(a.E[C]);
+    const double Eo = (double)Ec[q];
+    const T *Pc_ = static_cast<const T *>(a.Pcur[C]);
+    T *Pn_ = static_cast<T *>(a.Pnew[C]);
+    double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxTerms; ++p) {
+        if (p >= a.nterm) break;
+        const bool drude = a.coef[kCoefHead + kCoefMode * p + 5] != 0.0;
+        pc[p] = (double)__builtin_nontemporal_load(Pc_ + (long long)p * a.mcells + m);
+        pp[p] = drude ? 0.0 : (double)__builtin_nontemporal_load(Pn_ + (long long)p * a.mcells + m);
+        dsum += pc[p] - pp[p];
+    }
+    double amp[kMaxSources];
+    load_amps(a, amp);
+    const double curl = t1 - t2;
+    const double En = Eo + a.inv_eps * (a.dt * curl - dsum) - source_term(a, amp, C, i, j, k);
+#pragma unroll
+    for (int p = 0; p < kMaxTerms; ++p) {
+        if (p >= a.nterm) break;
+        const double *tc = a.coef + kCoefHead + kCoefMode * p;
+        const bool drude = tc[5] != 0.0;
+        __builtin_nontemporal_store((T)(drude ? tc[0] * En + tc[1] * pc[p] : tc[0] * tc[6] * En - tc[1] * pc[p] - tc[2] * pp[p]),
+                                    Pn_ + (long long)p * a.mcells + m);
+    }
+    Ec[q] = (T)En;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBathBlock) void k_update_e_multi_c(const EArgs a) {
+    const int nbc = gridDim.x / 3;                  // blocks per component
+    const int c = blockIdx.x / nbc;
+    const int t = (blockIdx.x - c * nbc) * kBathBlock + threadIdx.x;
+    if (t >= a.ext[0] * a.ext12) return;
+    if (c == 0) multi_component<T, 0>(a, t);
+    else if (c == 1) multi_component<T, 1>(a, t);
+    else multi_component<T, 2>(a, t);
+}
+
+// ---------------------------------------------------------------------------------------------
 // The same update with the bath coordinates stored in 16 bits (a reduced-precision storage mode,
 // reported apart from the FP32 path): YF = 1 IEEE binary16 of Y times a scale s (a power of two keeps
 // the scaling exact), YF = 2 bfloat16 (the upper half of the binary32 pattern) of Y times s.  Eight
@@ -1795,6 +1852,13 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
             else
                 hipLaunchKernelGGL((k_update_e_bath<DIM, T, NG, false>),
                                    dim3(nblocks(DIM == 3 ? pair_threads(a.ext) : n)), dim3(kBlock), 0, s, a, cf);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (KIND == K_MULTI && DIM == 3 && !PML) {
+        if (!a.bloch && !energy) {
+            hipLaunchKernelGGL(k_update_e_multi_c<T>, dim3(3 * (unsigned)((n + kBathBlock - 1) / kBathBlock)),
+                               dim3(kBathBlock), 0, s, a);
             return hipGetLastError();
         }
     }
