@@ -210,7 +210,9 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
  * returns the flux of the complex fields Re sum (E~ x conj H~) with E~ = E~_re + i E~_im (its raw
  * output: re's accumulators), fdtdb_dft_flux(im, id, NULL, raw) only im's accumulators; energies,
  * fields and material state are read per part (the conserved energy is the sum over both parts,
- * so the energy-growth watchdog is off on pairs).  Bloch grids run the generic per-cell kernels.
+ * so the energy-growth watchdog is off on pairs).  Only the rows whose neighbour read crosses a Bloch
+ * axis (E's first row, H's last row along it) read the other part; they run the generic per-cell
+ * kernels, every other region the kernels of a real grid.
  * Destroying one part leaves the other unable to step (E_STATE).  Errors: E_INVALID for mismatched
  * grids, a phase on a non-periodic axis or a flux plane normal to a Bloch axis at its first cell;
  * E_STATE when either grid has stepped, is already paired or holds a learned closure, a bath stored
