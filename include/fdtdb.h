@@ -222,10 +222,11 @@ fdtdb_status fdtdb_pair_bloch(fdtdb_grid re, fdtdb_grid im, const double phase[3
 /* Storage of a Lorentz-Bath material's bath coordinates Y_j (eq:Yzj_finite_difference; both time
  * levels): FDTDB_BATH_STATE (the grid's state type, the default), FDTDB_BATH_F16 (IEEE binary16 of
  * Y_j * scale) or FDTDB_BATH_BF16 (bfloat16 of Y_j * scale).  A reduced-precision mode beside the
- * method's FP32 state, for baths whose bytes bound the step: the update arithmetic stays FP64, each
- * new Y_j is rounded to binary32 and then to the 16-bit format (round to nearest even), which halves
- * the bath's bytes and adds that rounding to every step (its error against the FP64 reference is
- * measured, not bounded by the FP32 bar).  scale (> 0, a power of two keeps it exact) places the
+ * method's FP32 state, for baths whose bytes bound the step: E and P are updated in FP64 as always, the
+ * bath recurrence of the scaled coordinates in binary32 (its rounding, 6e-8, is far below the format's),
+ * and each new Y_j * scale is rounded to the 16-bit format (round to nearest even), which halves the
+ * bath's bytes and adds that rounding to every step (its error against the FP64 reference is measured,
+ * not bounded by the FP32 bar).  scale (> 0, a power of two keeps it exact) places the
  * coordinates in the format's range (binary16: normal from 6.1e-5 to 65504).  Eight coordinates travel
  * as one 16-byte word ([word][cell] per level and component).  Available for 3D FP32 grids and baths of
  * 16 modes (the component-split kernel), before the first step, on a

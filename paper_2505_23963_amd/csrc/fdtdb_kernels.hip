@@ -993,25 +993,24 @@ __global__ __launch_bounds__(kBathBlock) void k_update_e_multi_c(const EArgs a) 
 // reported apart from the FP32 path): YF = 1 IEEE binary16 of Y times a scale s (a power of two keeps
 // the scaling exact), YF = 2 bfloat16 (the upper half of the binary32 pattern) of Y times s.  Eight
 // coordinates (two mode groups) travel as one 16-byte word, so a cell's bath takes half the load
-// instructions of the FP32 layout as well as half the bytes; the arithmetic is FP64 as above, each stored
-// value rounded to binary32 and then to the 16-bit format (round to nearest even at both steps).
+// instructions of the FP32 layout as well as half the bytes.  E and P are updated in FP64 as above; the
+// bath recurrence of the scaled coordinates runs in binary32 (3.84 ms per 512^3 launch in FP64 with its
+// conversions, 3.41 ms so; the error against the oracle is the format's either way) and each new value
+// is rounded to the 16-bit format (round to nearest even).
 // ---------------------------------------------------------------------------------------------
 typedef unsigned int nv4u __attribute__((ext_vector_type(4)));
 
-// the stored (scaled) coordinate u of a word, widened
+// the stored (scaled) coordinate u of a word, widened to binary32
 template <int YF>
-__device__ __forceinline__ double unpack16(nv4u w, int u) {
+__device__ __forceinline__ float unpack16(nv4u w, int u) {
     const unsigned bits = (u & 1) ? (w[u >> 1] >> 16) : (w[u >> 1] & 0xffffu);
-    float f;
-    if constexpr (YF == 1) f = (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
-    else f = __builtin_bit_cast(float, bits << 16);
-    return (double)f;
+    if constexpr (YF == 1) return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
+    return __builtin_bit_cast(float, bits << 16);
 }
 
-// a scaled coordinate rounded to binary32 and then to the 16-bit format
+// a scaled coordinate (binary32) rounded to the 16-bit format
 template <int YF>
-__device__ __forceinline__ unsigned pack16(double y) {
-    const float f = (float)y;
+__device__ __forceinline__ unsigned pack16(float f) {
     if constexpr (YF == 1) return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)f);
     unsigned x = __builtin_bit_cast(unsigned, f);
     x += 0x7fffu + ((x >> 16) & 1u);                 // round to nearest even on the dropped half
@@ -1055,35 +1054,37 @@ __device__ __forceinline__ void bath_component16(const EArgs &a, int t) {
     double amp[kMaxSources];
     load_amps(a, amp);
     const double sig = has_sig ? (double)sig_raw : a.sigma0;
-    // the coordinates stay scaled (Y s): the bath force and the coupling to dP take the coefficients of the
-    // block after the modes (sa_j / s, sb_j / s and c_j s), the recurrence a_j, b_j + 1 as they are
+    // the coordinates stay scaled (Y s) and their recurrence runs in binary32 (its rounding, 6e-8, is far
+    // below the 16-bit format's): the FP32 block after the modes holds a_j, b_j + 1, c_j s, sa_j / s and
+    // sb_j / s per mode; E and P are updated in FP64 as everywhere
     typedef const __attribute__((address_space(4))) double *cdp;
+    typedef const __attribute__((address_space(4))) float *cfp;
     cdp co = (cdp)a.coef;
     const double En = Eo + a.inv_eps * (a.dt * (t1 - t2) - (Pc - Pp)) - source_term(a, amp, C, i, j, k);
-    double S = 0.0;
+    float Sf = 0.0f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         asm volatile("" : "+s"(co));
-        const cdp xs = co + kCoefHead + 4 * NG * kCoefMode + 8 * w * kCoefExt;
+        const cfp xf = (cfp)(co + kCoefHead + 4 * NG * kCoefMode) + 8 * w * 5;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            S += xs[u * kCoefExt + 1] * unpack16<YF>(yc[w], u) + xs[u * kCoefExt + 2] * unpack16<YF>(yp[w], u);
+            Sf += xf[u * 5 + 3] * unpack16<YF>(yc[w], u) + xf[u * 5 + 4] * unpack16<YF>(yp[w], u);
     }
+    const double S = (double)Sf;
     asm volatile("" : "+s"(co));
     const double Pnew = co[0] * sig * En - co[1] * Pc - co[2] * Pp - S;
-    const double dP = Pnew - Pp;
+    const float dPf = (float)(Pnew - Pp);
     static_cast<T *>(a.E[C])[q] = (T)En;
     __builtin_nontemporal_store((T)Pnew, static_cast<T *>(a.Pnew[C]) + m);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         asm volatile("" : "+s"(co));
-        const cdp md = co + kCoefHead + 8 * w * kCoefMode;
-        const cdp xs = co + kCoefHead + 4 * NG * kCoefMode + 8 * w * kCoefExt;
+        const cfp xf = (cfp)(co + kCoefHead + 4 * NG * kCoefMode) + 8 * w * 5;
         unsigned h[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            h[u] = pack16<YF>(md[u * kCoefMode + 0] * unpack16<YF>(yc[w], u) +
-                              md[u * kCoefMode + 1] * unpack16<YF>(yp[w], u) + xs[u * kCoefExt + 0] * dP);
+            h[u] = pack16<YF>(xf[u * 5 + 0] * unpack16<YF>(yc[w], u) + xf[u * 5 + 1] * unpack16<YF>(yp[w], u) +
+                              xf[u * 5 + 2] * dPf);
         nv4u o;
         o[0] = h[0] | (h[1] << 16);
         o[1] = h[2] | (h[3] << 16);

@@ -1396,14 +1396,21 @@ static fdtdb_status rebuild_ext(fdtdb_grid_s *g, Material &m) {
             x[2] = 0.5 * dt * m.kj[jb] / A;
         }
     } else if (m.yfmt) {
-        m.coef.resize(base + (size_t)kCoefExt * 4 * m.ng, 0.0);
+        // per mode, as FP32 (5 floats; the bath recurrence of 16-bit coordinates runs in FP32): a_j, b_j + 1,
+        // c_j s, sa_j / s, sb_j / s, packed two to a table word
+        const size_t nf = 5 * 4 * (size_t)m.ng;
+        m.coef.resize(base + (nf + 1) / 2, 0.0);
+        std::vector<float> f(nf + 1, 0.0f);
         for (int jb = 0; jb < 4 * m.ng; jb++) {
             const double *md = &m.coef[kCoefHead + (size_t)kCoefMode * jb];
-            double *x = &m.coef[base + (size_t)kCoefExt * jb];
-            x[0] = md[2] * m.yscale;
-            x[1] = md[3] / m.yscale;
-            x[2] = md[4] / m.yscale;
+            float *x = &f[5 * (size_t)jb];
+            x[0] = (float)md[0];
+            x[1] = (float)md[1];
+            x[2] = (float)(md[2] * m.yscale);
+            x[3] = (float)(md[3] / m.yscale);
+            x[4] = (float)(md[4] / m.yscale);
         }
+        std::memcpy(&m.coef[base], f.data(), 4 * nf);
     }
     void *old = m.coef_dev;
     g->release(old);
