@@ -642,7 +642,9 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
 // arithmetic or store, with neighbour reads branch-free, so a wave keeps its whole working set
 // in flight; the bath coefficients arrive by value in the kernel arguments (scalar loads).
 // E, P and the bath are then advanced in FP64 registers and written once.  Used when the bath
-// of all components fits the register budget (components x groups <= 16).
+// of all components fits the register budget (components x groups <= 16).  In 2D it also takes
+// the wrap rows of a Bloch pair, whose wrapped lower neighbour mixes in the other part (a launch
+// elsewhere has no other part and reads as on a real grid).
 // ---------------------------------------------------------------------------------------------
 template <int DIM, typename T, int NG, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const BathCoef<NG> cf) {
@@ -712,14 +714,16 @@ __global__ __launch_bounds__(kBlock) void k_update_e_bath(const EArgs a, const B
                 t1[ci] = (double)own -
                          (kPairs ? minus_lane_pairs<T>(a.H[a2], own, q, a1, coord[a1], stride[a1], a.n[a1], a.per[a1])
                           : DIM == 3 && a1 == 2 ? z_minus_lane<T>(a.H[a2], own, q, k, a.lo[2], a.n[2], a.per[2])
-                                                : at_minus<T>(a.H[a2], q, coord[a1], stride[a1], a.n[a1], a.per[a1]));
+                                                : at_minus_bloch<T>(a.H[a2], a.Htw[a2], q, coord[a1], stride[a1], a.n[a1],
+                                                                    a.per[a1], a.bcos[a1], a.bsin[a1]));
             }
             if (axis_live(DIM, a2) && h_active(DIM, a1)) {
                 const T own = static_cast<const T *>(a.H[a1])[q];
                 t2[ci] = (double)own -
                          (kPairs ? minus_lane_pairs<T>(a.H[a1], own, q, a2, coord[a2], stride[a2], a.n[a2], a.per[a2])
                           : DIM == 3 && a2 == 2 ? z_minus_lane<T>(a.H[a1], own, q, k, a.lo[2], a.n[2], a.per[2])
-                                                : at_minus<T>(a.H[a1], q, coord[a2], stride[a2], a.n[a2], a.per[a2]));
+                                                : at_minus_bloch<T>(a.H[a1], a.Htw[a1], q, coord[a2], stride[a2], a.n[a2],
+                                                                    a.per[a2], a.bcos[a2], a.bsin[a2]));
             }
             Eo[ci] = (double)static_cast<const T *>(a.E[c])[q];
             // polarization and bath levels are read once and written once per step: stream them
@@ -1814,9 +1818,10 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
     const long long n = (long long)a.ext[0] * a.ext12;
     if (n == 0) return hipSuccess;
     constexpr int NC = DIM == 3 ? 3 : 1;
-    // the specialised bath kernels read no other part: real grids only (a Bloch pair takes k_update_e);
-    // of them only the component-split kernel carries the thermal / anharmonic terms (without energy
-    // sampling), other extended baths take k_update_e
+    // of the specialised bath kernels only the 2D load-first one reads the other part of a Bloch pair
+    // (the wrap rows; other launches of a pair are real-grid launches); of them only the component-split
+    // kernel carries the thermal / anharmonic terms (without energy sampling), other extended baths take
+    // k_update_e
     if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16 && DIM == 3 && NC * NG > 6) {
         if (!a.bloch && a.bext && !energy) {
             // no occupancy cap: with the noise generator the kernel is bound by its arithmetic as much as by
@@ -1829,7 +1834,7 @@ static hipError_t launch_e_pml(const EArgs &a, const double *coef_host, bool ene
         }
     }
     if constexpr (KIND == K_BATH && !PML && NG > 0 && NC * NG <= 16) {
-        if (!a.bloch && !a.bext) {
+        if ((!a.bloch || DIM == 2) && !a.bext) {
             BathCoef<NG> cf;
             for (int h = 0; h < 3; ++h) cf.head[h] = coef_host[h];
             for (int j = 0; j < 4 * NG; ++j)

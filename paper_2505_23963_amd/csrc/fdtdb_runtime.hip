@@ -109,7 +109,8 @@ struct Region {
     void *psiH[3][2] = {};
     bool energy = false;
     // on a Bloch pair: the region reads the other part (E: the first row along a Bloch axis, whose lower
-    // neighbour wraps; H: the last row, whose upper neighbour wraps) and takes the generic kernels
+    // neighbour wraps; H: the last row, whose upper neighbour wraps) and takes the generic kernels; a 2D
+    // Lorentz-Bath material touching the wrap is one such region as a whole, on its load-first kernel
     bool wrap = false;
     long long block_base = 0;
     // H only: z-term psi for z < zlo and z >= zhi alone, in zw = (zlo - lo) + (hi - zhi) slots per
@@ -350,6 +351,16 @@ int upper_pml_cut(const fdtdb_grid_s *g, int a, bool h) {
     return std::max(g->pml[a], vec_axis ? (cut - 1) & ~31 : cut - 1);
 }
 
+// a 2D Lorentz-Bath material on a Bloch pair that touches the wrap: its load-first kernel reads the other
+// part in the wrap rows itself, so the whole material is one region that reads across the wrap rather than
+// a region plus a one-row launch of the generic kernel (2048 x 1024 grid, N_b = 64: two 28 us launches a step)
+bool bath_reads_wrap(const fdtdb_grid_s *g, const Material &m) {
+    if (!g->twin || g->ndim != 2 || m.kind != K_BATH || m.ng <= 0 || m.ng > 16 || m.bext() || m.yfmt) return false;
+    for (int a = 0; a < 2; a++)
+        if (g->bph[a] != 0.0 && m.lo[a] == 0) return true;
+    return false;
+}
+
 void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) {
     const bool h = !with_mats;
     std::vector<int> br[3];
@@ -392,6 +403,7 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                     if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= up[a])) mask |= 1 << a;
                 for (int a = 0; g->twin && a < g->ndim; a++)     // bit 8: a row that reads across a Bloch axis
                     if (g->bph[a] != 0.0 && lo[a] == (h ? g->n[a] - 1 : 0)) mask |= 1 << 8;
+                if (mat >= 0 && bath_reads_wrap(g, g->mats[mat])) mask |= 1 << 8;
                 auto k = std::make_pair(mat, mask);
                 if (!ids.count(k)) {
                     int id = (int)ids.size();
