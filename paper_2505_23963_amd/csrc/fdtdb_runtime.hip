@@ -351,6 +351,15 @@ int upper_pml_cut(const fdtdb_grid_s *g, int a, bool h) {
     return std::max(g->pml[a], vec_axis ? (cut - 1) & ~31 : cut - 1);
 }
 
+// rows at each end of a Bloch axis that go into the wrap regions: one, or four along the axis the vector
+// kernels run along (z in 3D, y in 2D) when its length is a multiple of 4, so that the regions between
+// stay 4-aligned and take those kernels (only the end row reads the other part; the other three are
+// updated as anywhere else)
+int wrap_rows(const fdtdb_grid_s *g, int a) {
+    const bool vec_axis = (g->ndim == 3 && a == 2) || (g->ndim == 2 && a == 1);
+    return vec_axis && g->n[a] % 4 == 0 && g->n[a] >= 8 ? 4 : 1;
+}
+
 // a 2D Lorentz-Bath material on a Bloch pair that touches the wrap: its load-first kernel reads the other
 // part in the wrap rows itself, so the whole material is one region that reads across the wrap rather than
 // a region plus a one-row launch of the generic kernel (2048 x 1024 grid, N_b = 64: two 28 us launches a step)
@@ -378,7 +387,7 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 br[a].push_back((int)m.lo[a]);
                 br[a].push_back((int)m.hi[a]);
             }
-        if (g->twin && a < g->ndim && g->bph[a] != 0.0) br[a].push_back(h ? (int)g->n[a] - 1 : 1);
+        if (g->twin && a < g->ndim && g->bph[a] != 0.0) br[a].push_back(h ? (int)g->n[a] - wrap_rows(g, a) : wrap_rows(g, a));
         std::sort(br[a].begin(), br[a].end());
         br[a].erase(std::unique(br[a].begin(), br[a].end()), br[a].end());
     }
@@ -391,6 +400,7 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
         for (int y = 0; y < nb; y++)
             for (int z = 0; z < nc; z++) {
                 const int64_t lo[3] = {br[0][x], br[1][y], br[2][z]};
+                const int64_t hi[3] = {br[0][x + 1], br[1][y + 1], br[2][z + 1]};
                 int mat = -1;
                 for (size_t mi = 0; with_mats && mi < g->mats.size(); mi++) {
                     const Material &m = g->mats[mi];
@@ -401,8 +411,8 @@ void partition(const fdtdb_grid_s *g, bool with_mats, std::vector<Region> &out) 
                 int mask = 0;
                 for (int a = 0; a < g->ndim; a++)
                     if (g->bc[a] == FDTDB_BC_PML && (lo[a] < g->pml[a] || lo[a] >= up[a])) mask |= 1 << a;
-                for (int a = 0; g->twin && a < g->ndim; a++)     // bit 8: a row that reads across a Bloch axis
-                    if (g->bph[a] != 0.0 && lo[a] == (h ? g->n[a] - 1 : 0)) mask |= 1 << 8;
+                for (int a = 0; g->twin && a < g->ndim; a++)     // bit 8: holds a row that reads across a Bloch axis
+                    if (g->bph[a] != 0.0 && (h ? hi[a] == g->n[a] : lo[a] == 0)) mask |= 1 << 8;
                 if (mat >= 0 && bath_reads_wrap(g, g->mats[mat])) mask |= 1 << 8;
                 auto k = std::make_pair(mat, mask);
                 if (!ids.count(k)) {
