@@ -957,13 +957,22 @@ __device__ __forceinline__ void multi_component(const EArgs &a, int t) {
     const double Eo = (double)Ec[q];
     const T *Pc_ = static_cast<const T *>(a.Pcur[C]);
     T *Pn_ = static_cast<T *>(a.Pnew[C]);
-    double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+    // every term's levels are loaded before any is used, so that they stream together rather than one
+    // term per memory round trip; the sum then runs over the terms in order
+    T pcr[kMaxTerms], ppr[kMaxTerms];
 #pragma unroll
     for (int p = 0; p < kMaxTerms; ++p) {
         if (p >= a.nterm) break;
         const bool drude = a.coef[kCoefHead + kCoefMode * p + 5] != 0.0;
-        pc[p] = (double)__builtin_nontemporal_load(Pc_ + (long long)p * a.mcells + m);
-        pp[p] = drude ? 0.0 : (double)__builtin_nontemporal_load(Pn_ + (long long)p * a.mcells + m);
+        pcr[p] = __builtin_nontemporal_load(Pc_ + (long long)p * a.mcells + m);
+        ppr[p] = drude ? (T)0 : __builtin_nontemporal_load(Pn_ + (long long)p * a.mcells + m);
+    }
+    double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxTerms; ++p) {
+        if (p >= a.nterm) break;
+        pc[p] = (double)pcr[p];
+        pp[p] = (double)ppr[p];
         dsum += pc[p] - pp[p];
     }
     double amp[kMaxSources];
