@@ -212,7 +212,9 @@ fdtdb_status fdtdb_add_energy_monitor(fdtdb_grid g, const fdtdb_box *box, int ev
  * fields and material state are read per part (the conserved energy is the sum over both parts,
  * so the energy-growth watchdog is off on pairs).  Only the rows whose neighbour read crosses a Bloch
  * axis (E's first row, H's last row along it) read the other part; they run the generic per-cell
- * kernels, every other region the kernels of a real grid.
+ * kernels (in wrap regions four rows deep along z in 3D, y in 2D, when that length is a multiple of
+ * 4), every other region the kernels of a real grid; in 2D a Lorentz-Bath material of up to 64 modes
+ * that touches the wrap runs as a whole on its own kernel, which reads the other part at the wrap.
  * Destroying one part leaves the other unable to step (E_STATE).  Errors: E_INVALID for mismatched
  * grids, a phase on a non-periodic axis or a flux plane normal to a Bloch axis at its first cell;
  * E_STATE when either grid has stepped, is already paired or holds a learned closure, a bath stored
