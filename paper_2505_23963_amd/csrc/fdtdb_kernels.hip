@@ -506,13 +506,21 @@ __global__ __launch_bounds__(kBlock) void k_update_e(const EArgs a) {
                 // and advances by V' = cE E + cV V, written to the other buffer (coefficients per term in the table)
                 T *Pc_ = static_cast<T *>(a.Pcur[c]);
                 T *Pn_ = static_cast<T *>(a.Pnew[c]);
-                double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+                // every term's levels are loaded before any is used (they stream together), then summed in order
+                T pcr[kMaxTerms], ppr[kMaxTerms];
 #pragma unroll
                 for (int p = 0; p < kMaxTerms; ++p) {
                     if (p >= a.nterm) break;
                     const bool drude = a.coef[kCoefHead + kCoefMode * p + 5] != 0.0;
-                    pc[p] = (double)Pc_[(long long)p * a.mcells + m];
-                    pp[p] = drude ? 0.0 : (double)Pn_[(long long)p * a.mcells + m];
+                    pcr[p] = Pc_[(long long)p * a.mcells + m];
+                    ppr[p] = drude ? (T)0 : Pn_[(long long)p * a.mcells + m];
+                }
+                double pc[kMaxTerms], pp[kMaxTerms], dsum = 0.0;
+#pragma unroll
+                for (int p = 0; p < kMaxTerms; ++p) {
+                    if (p >= a.nterm) break;
+                    pc[p] = (double)pcr[p];
+                    pp[p] = (double)ppr[p];
                     dsum += pc[p] - pp[p];
                 }
                 En = Eo + R.inv_eps * (a.dt * curl - dsum) - srcterm;
