@@ -168,6 +168,7 @@ struct EArgs {
     void *hid[3];                    // learned closure hidden state [mcells] of float4
     const float *cw;                 // learned closure weights (FP32, kClosureParams)
     int nterm;                       // multi-term material: terms, each with its levels [term][mcells] in Pcur / Pnew
+    int drude_mask;                  // multi-term material: bit p set when term p is a Drude term
     // bath coordinate storage: 0 the state type, 1 binary16 of Y yscale, 2 bfloat16 of Y yscale (yinv = 1 / yscale)
     int yfmt;
     double yscale, yinv;

@@ -971,7 +971,7 @@ __device__ __forceinline__ void multi_component(const EArgs &a, int t) {
 #pragma unroll
     for (int p = 0; p < kMaxTerms; ++p) {
         if (p >= a.nterm) break;
-        const bool drude = a.coef[kCoefHead + kCoefMode * p + 5] != 0.0;
+        const bool drude = (a.drude_mask >> p) & 1;     // from the launch arguments: no load between the terms' loads
         pcr[p] = __builtin_nontemporal_load(Pc_ + (long long)p * a.mcells + m);
         ppr[p] = drude ? (T)0 : __builtin_nontemporal_load(Pn_ + (long long)p * a.mcells + m);
     }

@@ -827,6 +827,9 @@ fdtdb_status enqueue_e(fdtdb_grid_s *g) {
                     a.Pnew[c] = m.P[nxt][c];
                 }
                 a.nterm = m.nterm;
+                a.drude_mask = 0;
+                for (int t = 0; t < m.nterm; t++)
+                    if (m.coef[kCoefHead + kCoefMode * t + 5] != 0.0) a.drude_mask |= 1 << t;
             } else if (kind == K_BATH || kind == K_CLOSURE) {
                 for (int c = 0; c < 3; c++) {
                     a.Pcur[c] = m.P[cur][c];
